@@ -1,0 +1,157 @@
+/*
+ * libaidw -- Adaptive Inverse Distance Weighting on AMD Instinct MI355X
+ * (gfx950), after Mei, Xu & Xu, "Accelerating Adaptive IDW Interpolation
+ * Algorithm on a Single GPU" (arXiv 1511.02186).
+ *
+ * For every interpolated (query) point the library runs the paper's two full
+ * passes over all m data points (Sec. 3.2, naive and tiled versions):
+ *   pass 1: the k nearest data points -> r_obs (Eq. 3), R = r_obs / r_exp
+ *           (Eq. 2, 4), mu_R (Eq. 5), the adaptive power alpha (Eq. 6);
+ *   pass 2: Z = sum(d_i^-alpha z_i) / sum(d_i^-alpha) over all m points
+ *           (Eq. 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Geometry is 2-D.  Point sets are PLANAR structure-of-arrays in DEVICE
+ *    memory: data_xy is [2][m] (the m x coordinates, then the m y
+ *    coordinates), data_z is [m], query_xy is [2][n], out is [n].  The element
+ *    type is float for AIDW_FP32_SCALED and double for AIDW_FP64.  Every
+ *    pointer must be aligned to its element size.
+ *  - The caller owns every buffer it passes; the library never frees or
+ *    retains them past the call (or, for asynchronous calls, past the work's
+ *    completion on the handle's stream).
+ *  - Arguments are validated on the host before any device work.  On error
+ *    nothing is launched, `out` is left untouched, and aidw_last_error()
+ *    returns a message for the calling thread.
+ *  - n == 0 is a valid no-op.
+ *  - Work is issued on the handle's stream (aidw_set_stream; the NULL stream
+ *    by default).  Unless AIDW_FLAG_ASYNC is given, calls return after the
+ *    work has completed.
+ *  - Handles are not thread-safe: use one handle per host thread.
+ *
+ * Readings of points the paper leaves open:
+ *  - m in Eq. 2 is the number of data points (Sec. 2 names it n; Sec. 3
+ *    renames it m); the study area A (`area`) is supplied by the caller.
+ *  - Eq. 5 is evaluated literally with the argument (pi / R_max)(R - R_min);
+ *    where the closed intervals of Eq. 5 and Eq. 6 overlap, the first listed
+ *    case applies.
+ *  - A query that coincides with data points (d = 0) returns the mean z of
+ *    those points when alpha > 0; when alpha == 0 all weights are 1.
+ *  - Equal distances in the kNN keep the smaller data index first.
+ */
+#ifndef AIDW_H
+#define AIDW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AIDW_VERSION_MAJOR 0
+#define AIDW_VERSION_MINOR 1
+
+/* Largest supported k (neighbours kept in registers per query). */
+#define AIDW_KMAX 32
+
+typedef enum aidw_status {
+    AIDW_OK = 0,
+    AIDW_EINVAL = -1,   /* an argument is out of its documented range */
+    AIDW_ENOMEM = -2,   /* device or host allocation failed */
+    AIDW_EDEVICE = -3,  /* a HIP call failed; the handle should be destroyed */
+    AIDW_EAGAIN = -4,   /* not finished yet */
+    AIDW_ENOTFOUND = -5 /* unknown ticket or dataset id */
+} aidw_status;
+
+typedef enum aidw_precision {
+    /* float inputs and output; FP32 pair arithmetic with weights rescaled per
+     * query as (d_min^2 / d^2)^(alpha/2) = exp2((alpha/2)(log2 d_min^2 -
+     * log2 d^2)), FP32 partial sums folded into FP64 accumulators, FP64
+     * r_obs / R / mu_R / alpha and final division. */
+    AIDW_FP32_SCALED = 0,
+    /* double inputs and output; plain FP64: d^2 without FMA contraction,
+     * weights pow(d, -alpha), compensated FP64 sums. */
+    AIDW_FP64 = 1
+} aidw_precision;
+
+/* Flags for aidw_problem.flags. */
+#define AIDW_FLAG_ASYNC 1u /* return once the work is queued on the stream */
+
+typedef struct aidw_options {
+    int device;                        /* HIP device ordinal */
+    aidw_precision default_precision;  /* used by aidw_interpolate() */
+    size_t hbm_budget_bytes;           /* cap on library-owned device memory; 0 = none */
+} aidw_options;
+
+typedef struct aidw_ctx* aidw_t;
+
+/* One AIDW problem.  Pointer fields are device pointers unless stated. */
+typedef struct aidw_problem {
+    aidw_precision precision;
+    const void* data_xy;     /* [2][m] planar x row then y row */
+    const void* data_z;      /* [m] */
+    int64_t m;               /* data points, 1 <= m <= 2^31 - 1 */
+    const void* query_xy;    /* [2][n] planar */
+    int64_t n;               /* queries, 0 <= n <= 2^31 - 1 */
+    int k;                   /* neighbours for r_obs (Eq. 3), 1 <= k <= min(m, AIDW_KMAX) */
+    double alpha_levels[5];  /* alpha_1..alpha_5 of Eq. 6; finite, >= 0 */
+    double R_min, R_max;     /* Eq. 5 bounds; R_max > R_min, R_max > 0 */
+    double area;             /* A of Eq. 2; finite, > 0 */
+    void* out;               /* [n] interpolated values (float or double) */
+    double* r_obs;           /* optional [n] observed mean kNN distance, or NULL */
+    double* alpha;           /* optional [n] adaptive power, or NULL */
+    int32_t* knn_idx;        /* optional [n][k] neighbour indices sorted by
+                                (distance, index), or NULL */
+    unsigned flags;          /* AIDW_FLAG_* */
+} aidw_problem;
+
+/* Create a handle on opt->device (opt may be NULL: device 0, FP32-scaled,
+ * no budget).  Returns AIDW_EINVAL for a bad device, AIDW_EDEVICE if HIP
+ * cannot be initialised. */
+aidw_status aidw_create(aidw_t* out, const aidw_options* opt);
+
+/* Wait for the handle's outstanding work, free library-owned memory and the
+ * handle.  NULL is ignored. */
+void aidw_destroy(aidw_t h);
+
+/* Issue subsequent work on `stream` (a hipStream_t of the handle's device,
+ * e.g. torch.cuda.current_stream().cuda_stream); NULL selects the default
+ * stream. */
+aidw_status aidw_set_stream(aidw_t h, void* stream);
+
+/* AIDW of n queries over m data points (Eq. 1-6), in the handle's default
+ * precision, synchronous.  Arguments as in aidw_problem; alpha_levels is a
+ * host array of 5 doubles. */
+aidw_status aidw_interpolate(aidw_t h, const void* data_xy, const void* data_z, int64_t m,
+                             const void* query_xy, int64_t n, int k,
+                             const double alpha_levels[5], double R_min, double R_max,
+                             double area, void* out);
+
+/* AIDW of one problem with an explicit precision, optional per-query
+ * diagnostics (r_obs, alpha, kNN indices) and flags. */
+aidw_status aidw_interpolate_ex(aidw_t h, const aidw_problem* p);
+
+/* Fix the launch shape used for FP32-scaled problems: each lane owns
+ * q_per_lane queries (1, 2 or 4).  0 restores the automatic choice, which
+ * depends on n and the device's compute-unit count.  Returns AIDW_EINVAL for
+ * other values. */
+aidw_status aidw_set_tuning(aidw_t h, int q_per_lane);
+
+/* Wait until all work issued on the handle's stream has finished. */
+aidw_status aidw_synchronize(aidw_t h);
+
+/* Message describing the calling thread's most recent error ("" if none). */
+const char* aidw_last_error(void);
+
+/* Static name of a status code. */
+const char* aidw_status_string(aidw_status s);
+
+/* Library version as (major << 16) | minor. */
+int aidw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AIDW_H */

@@ -1,0 +1,258 @@
+"""Thin ctypes binding over libaidw.so (include/aidw.h).
+
+The functions below carry the C names and only marshal arguments: every step
+of the interpolation runs in the library's HIP kernels.  Tensors are torch
+tensors already resident on the GPU; the library is handed their device
+pointers and torch's current HIP stream.  If libaidw.so has not been built,
+loading fails with an error instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaidw.so")
+
+AIDW_OK = 0
+AIDW_EINVAL = -1
+AIDW_ENOMEM = -2
+AIDW_EDEVICE = -3
+AIDW_EAGAIN = -4
+AIDW_ENOTFOUND = -5
+
+AIDW_FP32_SCALED = 0
+AIDW_FP64 = 1
+
+AIDW_FLAG_ASYNC = 1
+AIDW_KMAX = 32
+
+
+class aidw_options(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("default_precision", ctypes.c_int),
+                ("hbm_budget_bytes", ctypes.c_size_t)]
+
+
+class aidw_problem(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int),
+        ("data_xy", ctypes.c_void_p),
+        ("data_z", ctypes.c_void_p),
+        ("m", ctypes.c_int64),
+        ("query_xy", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("k", ctypes.c_int),
+        ("alpha_levels", ctypes.c_double * 5),
+        ("R_min", ctypes.c_double),
+        ("R_max", ctypes.c_double),
+        ("area", ctypes.c_double),
+        ("out", ctypes.c_void_p),
+        ("r_obs", ctypes.c_void_p),
+        ("alpha", ctypes.c_void_p),
+        ("knn_idx", ctypes.c_void_p),
+        ("flags", ctypes.c_uint),
+    ]
+
+
+class AidwError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (status_name(status), message))
+        self.status = status
+
+
+_lib = None
+
+_SIGNATURES = {
+    "aidw_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(aidw_options)]),
+    "aidw_destroy": (None, [ctypes.c_void_p]),
+    "aidw_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "aidw_interpolate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_void_p]),
+    "aidw_interpolate_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem)]),
+    "aidw_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "aidw_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
+    "aidw_last_error": (ctypes.c_char_p, []),
+    "aidw_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "aidw_version": (ctypes.c_int, []),
+}
+
+
+def lib():
+    """Load libaidw.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libaidw.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_name(status: int) -> str:
+    return lib().aidw_status_string(int(status)).decode()
+
+
+def last_error() -> str:
+    return lib().aidw_last_error().decode()
+
+
+def check(status: int) -> int:
+    if status != AIDW_OK:
+        raise AidwError(status, last_error())
+    return status
+
+
+# ---- the C entry points, same names ---------------------------------------
+
+def aidw_create(device: int = 0, default_precision: int = AIDW_FP32_SCALED,
+                hbm_budget_bytes: int = 0) -> int:
+    h = ctypes.c_void_p()
+    opt = aidw_options(device, default_precision, hbm_budget_bytes)
+    check(lib().aidw_create(ctypes.byref(h), ctypes.byref(opt)))
+    return h.value
+
+
+def aidw_destroy(h) -> None:
+    lib().aidw_destroy(h)
+
+
+def aidw_set_stream(h, stream_ptr: int) -> int:
+    return lib().aidw_set_stream(h, stream_ptr)
+
+
+def aidw_interpolate(h, data_xy_ptr, data_z_ptr, m, query_xy_ptr, n, k, alpha_levels, R_min,
+                     R_max, area, out_ptr) -> int:
+    lv = (ctypes.c_double * 5)(*[float(a) for a in alpha_levels])
+    return lib().aidw_interpolate(h, data_xy_ptr, data_z_ptr, int(m), query_xy_ptr, int(n),
+                                  int(k), lv, float(R_min), float(R_max), float(area), out_ptr)
+
+
+def aidw_interpolate_ex(h, problem: aidw_problem) -> int:
+    return lib().aidw_interpolate_ex(h, ctypes.byref(problem))
+
+
+def aidw_set_tuning(h, q_per_lane: int) -> int:
+    return lib().aidw_set_tuning(h, int(q_per_lane))
+
+
+def aidw_synchronize(h) -> int:
+    return lib().aidw_synchronize(h)
+
+
+def aidw_version() -> int:
+    return lib().aidw_version()
+
+
+# ---- torch convenience layer ------------------------------------------------
+
+class Context:
+    """Owns one aidw handle bound to a device and torch's current stream."""
+
+    def __init__(self, device: int = 0, default_precision: int = AIDW_FP32_SCALED,
+                 hbm_budget_bytes: int = 0):
+        self.device = device
+        self.h = aidw_create(device, default_precision, hbm_budget_bytes)
+
+    def close(self):
+        if self.h:
+            aidw_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tuning(self, q_per_lane: int = 0):
+        check(aidw_set_tuning(self.h, q_per_lane))
+
+    def bind_current_stream(self):
+        import torch
+
+        check(aidw_set_stream(self.h, torch.cuda.current_stream(self.device).cuda_stream))
+
+    def problem(self, data_xy, data_z, query_xy, k, out, alpha_levels=(1, 2, 3, 4, 5),
+                R_min=0.0, R_max=2.0, area=None, r_obs=None, alpha=None, knn_idx=None,
+                flags=0) -> aidw_problem:
+        import torch
+
+        if area is None:
+            raise ValueError("area (A of Eq. 2) must be given")
+        dt = data_xy.dtype
+        prec = {torch.float32: AIDW_FP32_SCALED, torch.float64: AIDW_FP64}.get(dt)
+        if prec is None:
+            raise TypeError("point arrays must be float32 or float64, got %s" % dt)
+        for t in (data_z, query_xy, out):
+            if t.dtype != dt:
+                raise TypeError("all point arrays and out must share one dtype")
+        for t in (data_xy, data_z, query_xy, out, r_obs, alpha, knn_idx):
+            if t is not None and (not t.is_cuda or not t.is_contiguous()):
+                raise ValueError("tensors must be contiguous and on the GPU")
+        m = data_z.numel()
+        n = out.numel()
+        if data_xy.numel() != 2 * m or query_xy.numel() != 2 * n:
+            raise ValueError("data_xy must be [2, m] and query_xy [2, n]")
+        p = aidw_problem()
+        p.precision = prec
+        p.data_xy = data_xy.data_ptr()
+        p.data_z = data_z.data_ptr()
+        p.m = m
+        p.query_xy = query_xy.data_ptr()
+        p.n = n
+        p.k = int(k)
+        p.alpha_levels = (ctypes.c_double * 5)(*[float(a) for a in alpha_levels])
+        p.R_min, p.R_max, p.area = float(R_min), float(R_max), float(area)
+        p.out = out.data_ptr()
+        p.r_obs = r_obs.data_ptr() if r_obs is not None else None
+        p.alpha = alpha.data_ptr() if alpha is not None else None
+        p.knn_idx = knn_idx.data_ptr() if knn_idx is not None else None
+        p.flags = int(flags)
+        return p
+
+    def interpolate(self, data_xy, data_z, query_xy, k, alpha_levels=(1, 2, 3, 4, 5),
+                    R_min=0.0, R_max=2.0, area=None, diag=False, flags=0, out=None):
+        """AIDW of the queries over the data (torch tensors on the GPU).
+
+        Returns `out`, or (out, r_obs, alpha, knn_idx) with diag=True."""
+        import torch
+
+        n = query_xy.shape[-1]
+        dev = data_xy.device
+        if out is None:
+            out = torch.empty(n, dtype=data_xy.dtype, device=dev)
+        r_obs = alpha = knn = None
+        if diag:
+            r_obs = torch.empty(n, dtype=torch.float64, device=dev)
+            alpha = torch.empty(n, dtype=torch.float64, device=dev)
+            knn = torch.empty((n, int(k)), dtype=torch.int32, device=dev)
+        self.bind_current_stream()
+        p = self.problem(data_xy, data_z, query_xy, k, out, alpha_levels, R_min, R_max, area,
+                         r_obs, alpha, knn, flags)
+        check(aidw_interpolate_ex(self.h, p))
+        if diag:
+            return out, r_obs, alpha, knn
+        return out
+
+
+def to_device(inst, device="cuda"):
+    """Planar device tensors (data_xy [2, m], data_z [m], query_xy [2, n]) of a
+    workloads.Instance."""
+    import torch
+
+    return (torch.from_numpy(inst.data_xy()).to(device),
+            torch.from_numpy(inst.data_z.copy()).to(device),
+            torch.from_numpy(inst.query_xy()).to(device))

@@ -1,0 +1,86 @@
+// Device-side pieces of the alpha determination (Sec. 2.2) and the
+// register-resident k-nearest list (Sec. 3.1.2), shared by the FP32-scaled
+// and the FP64 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace aidw {
+
+// Eq. 5: mu_R in [0, 1]; the argument of the cosine is (pi / R_max)(R - R_min)
+// and the first case whose interval contains R is taken.
+__device__ __forceinline__ double eq5_mu(double R, double R_min, double R_max) {
+    if (R <= R_min) return 0.0;
+    if (R <= R_max) return 0.5 - 0.5 * cos((M_PI / R_max) * (R - R_min));
+    return 1.0;
+}
+
+// Eq. 6: triangular membership over the five levels, knots at
+// mu = 0.1, 0.3, 0.5, 0.7, 0.9, flat outside; first matching case taken.
+__device__ __forceinline__ double eq6_alpha(double mu, const double* lv) {
+    if (mu <= 0.1) return lv[0];
+    if (mu <= 0.3) return lv[0] * (1.0 - 5.0 * (mu - 0.1)) + 5.0 * lv[1] * (mu - 0.1);
+    if (mu <= 0.5) return 5.0 * lv[2] * (mu - 0.3) + lv[1] * (1.0 - 5.0 * (mu - 0.3));
+    if (mu <= 0.7) return lv[2] * (1.0 - 5.0 * (mu - 0.5)) + 5.0 * lv[3] * (mu - 0.5);
+    if (mu <= 0.9) return 5.0 * lv[4] * (mu - 0.7) + lv[3] * (1.0 - 5.0 * (mu - 0.7));
+    return lv[4];
+}
+
+// Eq. 3-6 for one query from its sorted list of squared distances t[0..K-1]
+// whose first K - k entries are -infinity.  Returns alpha; r_obs through
+// the reference.  Summed in ascending order in FP64.
+template <int K, typename T>
+__device__ __forceinline__ double alpha_from_list(const T (&t)[K], const AlphaParams& ap,
+                                                  double& r_obs) {
+    const int pad = K - ap.k;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        if (i >= pad) s += sqrt((double)t[i]);
+    r_obs = s / (double)ap.k;
+    const double R = r_obs / ap.r_exp;
+    return eq6_alpha(eq5_mu(R, ap.R_min, ap.R_max), ap.levels);
+}
+
+// The smallest real entry (index K - k) read with static indices only.
+template <int K, typename T>
+__device__ __forceinline__ T list_min(const T (&t)[K], int k) {
+    const int pad = K - k;
+    T v = t[K - 1];
+#pragma unroll
+    for (int i = 0; i < K; ++i) v = (i == pad) ? t[i] : v;
+    return v;
+}
+
+// Insert v into the ascending list t, dropping the largest entry: entry i
+// becomes the median of (t[i-1], v, t[i]).  Equal values do not move, so
+// a later-scanned point never displaces an earlier one at equal distance.
+template <int K>
+__device__ __forceinline__ void list_insert(float (&t)[K], float v) {
+#pragma unroll
+    for (int i = K - 1; i > 0; --i) t[i] = __builtin_amdgcn_fmed3f(t[i - 1], v, t[i]);
+    t[0] = fminf(t[0], v);
+}
+
+// Same insertion carrying the data index; strict comparisons keep the
+// earlier (smaller) index first among equal distances.
+template <int K, typename T>
+__device__ __forceinline__ void list_insert_idx(T (&t)[K], int (&ti)[K], T v, int vi) {
+#pragma unroll
+    for (int i = K - 1; i > 0; --i) {
+        const bool before_prev = v < t[i - 1];
+        const bool before_cur = v < t[i];
+        const T nt = before_prev ? t[i - 1] : (before_cur ? v : t[i]);
+        const int ni = before_prev ? ti[i - 1] : (before_cur ? vi : ti[i]);
+        t[i] = nt;
+        ti[i] = ni;
+    }
+    if (v < t[0]) {
+        t[0] = v;
+        ti[0] = vi;
+    }
+}
+
+}  // namespace aidw

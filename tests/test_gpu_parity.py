@@ -1,0 +1,321 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Error metric (primary): |z_gpu - z_ref| / (sum w|z| / sum w), the oracle's own
+weighted mean of |z| (obtained by running the oracle on |z|, since the weights
+do not depend on z).  Bars: FP32-scaled <= 1e-4; plain FP64 <= 1e-12 with
+kNN index sets identical to the oracle's (ties broken by data index).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1511_02186_amd import aidw, workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-4
+TOL_F64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    c = aidw.Context(0)
+    yield c
+    c.close()
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def gpu_run(ctx, torch, inst, diag=False, q_per_lane=0, query_index=None):
+    inst_q = inst if query_index is None else _subset(inst, query_index)
+    data_xy, data_z, query_xy = aidw.to_device(inst_q)
+    ctx.set_tuning(q_per_lane)
+    try:
+        res = ctx.interpolate(data_xy, data_z, query_xy, inst.k, inst.levels, inst.R_min,
+                              inst.R_max, inst.area, diag=diag)
+    finally:
+        ctx.set_tuning(0)
+    torch.cuda.synchronize()
+    if diag:
+        return tuple(t.cpu().numpy() for t in res)
+    return res.cpu().numpy()
+
+
+def _subset(inst, idx):
+    import copy
+
+    s = copy.copy(inst)
+    s.query_x = np.ascontiguousarray(inst.query_x[idx])
+    s.query_y = np.ascontiguousarray(inst.query_y[idx])
+    return s
+
+
+def ref(inst, idx=None, diag=False, levels=None):
+    qx = inst.query_x if idx is None else inst.query_x[idx]
+    qy = inst.query_y if idx is None else inst.query_y[idx]
+    lv = inst.levels if levels is None else levels
+    args = (inst.data_x, inst.data_y)
+    res = oracle.run(*args, inst.data_z, qx, qy, inst.k, lv, inst.R_min, inst.R_max, inst.area,
+                     diag=diag)
+    scale = oracle.run(*args, np.abs(inst.data_z), qx, qy, inst.k, lv, inst.R_min, inst.R_max,
+                       inst.area)
+    return res, scale
+
+
+def rel_err(got, want, scale):
+    diff = np.abs(np.asarray(got, dtype=np.float64) - want)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        e = np.where(scale > 0, diff / scale, np.where(diff == 0, 0.0, np.inf))
+    return e
+
+
+# ---- small single instance in FP64 and FP32 ------------------------------------
+
+def test_small_fp64_exact_knn_and_1e12(ctx, torch):
+    inst = workloads.uniform_small()  # m = n = 1024, k = 10, FP64, seed 0
+    out, r_obs, alpha, knn = gpu_run(ctx, torch, inst, diag=True)
+    (o_out, o_r, o_a, o_knn), scale = ref(inst, diag=True)
+    assert np.array_equal(knn.astype(np.int64), o_knn)
+    assert np.max(np.abs(r_obs - o_r) / o_r) <= 1e-14
+    assert np.max(np.abs(alpha - o_a)) <= 1e-13
+    err = rel_err(out, o_out, scale)
+    say("fp64 small: max err %.3e" % err.max())
+    assert err.max() <= TOL_F64
+
+
+def test_small_fp32_scaled(ctx, torch):
+    inst = workloads.uniform_small(dtype=np.float32)
+    out, r_obs, alpha, _ = gpu_run(ctx, torch, inst, diag=True)
+    (o_out, o_r, o_a, _), scale = ref(inst, diag=True)
+    err = rel_err(out, o_out, scale)
+    say("fp32 small: max err %.3e (vs |z|: %.3e)" % (err.max(),
+        np.max(np.abs(out - o_out) / np.maximum(np.abs(o_out), 1e-300))))
+    assert err.max() <= TOL_F32
+    assert np.max(np.abs(r_obs - o_r) / o_r) <= 1e-6
+    assert np.max(np.abs(alpha - o_a)) <= 1e-5
+
+
+@pytest.mark.parametrize("q", [1, 2, 4])
+def test_fp32_launch_shapes_agree(ctx, torch, q):
+    inst = workloads.paper_scale(m=3001, n=2 * 4 * 256 + 77, seed=21)
+    out = gpu_run(ctx, torch, inst, q_per_lane=q)
+    base = gpu_run(ctx, torch, inst, q_per_lane=1)
+    # the per-query arithmetic does not depend on the slot a query occupies
+    assert np.array_equal(out, base)
+    o, scale = ref(inst, idx=np.arange(0, inst.n, 7))
+    assert rel_err(out[::7], o, scale).max() <= TOL_F32
+
+
+# ---- every register bucket, ragged sizes --------------------------------------
+
+KS = [1, 2, 3, 4, 5, 8, 9, 10, 11, 12, 15, 16, 17, 20, 23, 24, 25, 31, 32]
+
+
+@pytest.mark.parametrize("k", KS)
+def test_ragged_sizes_all_k_fp64(ctx, torch, k):
+    inst = workloads.uniform_small(m=700 + 13 * k, n=333, seed=100 + k, k=k)
+    out, r_obs, alpha, knn = gpu_run(ctx, torch, inst, diag=True)
+    (o_out, o_r, o_a, o_knn), scale = ref(inst, diag=True)
+    assert np.array_equal(knn.astype(np.int64), o_knn)
+    assert rel_err(out, o_out, scale).max() <= TOL_F64
+
+
+@pytest.mark.parametrize("k", KS)
+def test_ragged_sizes_all_k_fp32(ctx, torch, k):
+    inst = workloads.paper_scale(m=900 + 17 * k, n=555, seed=200 + k, k=k)
+    out, _, alpha, knn = gpu_run(ctx, torch, inst, diag=True)
+    (o_out, _, o_a, o_knn), scale = ref(inst, diag=True)
+    assert rel_err(out, o_out, scale).max() <= TOL_F32
+    # FP32 squared distances may order near-ties differently from FP64: the
+    # selected sets must be valid k-nearest sets up to FP32 rounding.
+    for q in range(0, inst.n, 37):
+        assert len(set(knn[q])) == k and knn[q].min() >= 0 and knn[q].max() < inst.m
+        d_gpu = np.sort(np.hypot(inst.query_x[q] - inst.data_x[knn[q]].astype(np.float64),
+                                 inst.query_y[q] - inst.data_y[knn[q]].astype(np.float64)))
+        d_ref = np.sort(np.hypot(inst.query_x[q] - inst.data_x[o_knn[q]].astype(np.float64),
+                                 inst.query_y[q] - inst.data_y[o_knn[q]].astype(np.float64)))
+        assert np.allclose(d_gpu, d_ref, rtol=1e-6, atol=1e-9)
+
+
+# ---- edge cases -----------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("m,k", [(1, 1), (5, 5), (16, 3), (17, 16), (33, 32)])
+def test_minimal_data_sets(ctx, torch, dtype, m, k):
+    inst = workloads.uniform_small(m=m, n=70, seed=m + k, k=k, dtype=dtype)
+    inst.area = 1.0  # the unit square (one point has a zero-area bounding box)
+    out = gpu_run(ctx, torch, inst)
+    o, scale = ref(inst)
+    assert rel_err(out, o, scale).max() <= (TOL_F64 if dtype == np.float64 else TOL_F32)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_queries_on_data_points_return_their_values(ctx, torch, dtype):
+    inst = workloads.uniform_small(m=1000, n=300, seed=3, dtype=dtype)
+    idx = np.random.default_rng(0).choice(inst.m, 100, replace=False)
+    inst.query_x[:100] = inst.data_x[idx]
+    inst.query_y[:100] = inst.data_y[idx]
+    out = gpu_run(ctx, torch, inst)
+    assert np.array_equal(out[:100], inst.data_z[idx])
+    o, scale = ref(inst)
+    assert rel_err(out, o, scale).max() <= (TOL_F64 if dtype == np.float64 else TOL_F32)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_duplicate_data_points(ctx, torch, dtype):
+    inst = workloads.uniform_small(m=400, n=100, seed=4, dtype=dtype)
+    inst.data_x[200:300] = inst.data_x[:100]
+    inst.data_y[200:300] = inst.data_y[:100]
+    inst.query_x[:50] = inst.data_x[:50]
+    inst.query_y[:50] = inst.data_y[:50]
+    out = gpu_run(ctx, torch, inst)
+    want = (inst.data_z[:50].astype(np.float64) + inst.data_z[200:250]) / 2
+    assert np.allclose(out[:50], want, rtol=0, atol=1e-6 if dtype == np.float32 else 1e-15)
+    o, scale = ref(inst)
+    assert rel_err(out, o, scale).max() <= (TOL_F64 if dtype == np.float64 else TOL_F32)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_constant_power_of_two_field_is_exact(ctx, torch, dtype):
+    inst = workloads.uniform_small(m=777, n=250, seed=5, dtype=dtype)
+    inst.data_z[:] = 4.0
+    out = gpu_run(ctx, torch, inst)
+    assert np.all(out == 4.0)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("levels", [(0, 0, 0, 0, 0), (2, 2, 2, 2, 2), (0.5, 1.5, 2.5, 4, 6),
+                                    (6, 4, 2.5, 1.5, 0.5)])
+def test_other_alpha_levels(ctx, torch, dtype, levels):
+    inst = workloads.clustered(m=3000, n=500, seed=6, k=8, dtype=dtype)
+    inst.levels = levels
+    out, _, alpha, _ = gpu_run(ctx, torch, inst, diag=True)
+    (o, _, o_a, _), scale = ref(inst, diag=True)
+    assert np.max(np.abs(alpha - o_a)) <= (1e-12 if dtype == np.float64 else 1e-5)
+    assert rel_err(out, o, scale).max() <= (TOL_F64 if dtype == np.float64 else TOL_F32)
+    if len(set(levels)) == 1:
+        idw = oracle.idw(inst.data_x, inst.data_y, inst.data_z, inst.query_x, inst.query_y,
+                         levels[0])
+        assert rel_err(out, idw, scale).max() <= (TOL_F64 if dtype == np.float64 else TOL_F32)
+
+
+def test_empty_query_set_is_a_no_op(ctx, torch):
+    d = torch.rand(2, 10, device="cuda")
+    z = torch.rand(10, device="cuda")
+    q = torch.empty(2, 0, device="cuda")
+    out = torch.empty(0, device="cuda")
+    res = ctx.interpolate(d, z, q, 3, area=1.0, out=out)
+    assert res.numel() == 0
+
+
+@pytest.mark.parametrize("bad", [
+    dict(k=0), dict(k=11), dict(k=33), dict(area=0.0), dict(area=float("nan")),
+    dict(R_min=2.0, R_max=1.0), dict(R_min=-1.0, R_max=0.0),
+    dict(alpha_levels=(1, 2, -3, 4, 5)), dict(alpha_levels=(1, 2, float("inf"), 4, 5)),
+])
+def test_invalid_arguments_leave_output_untouched(ctx, torch, bad):
+    d = torch.rand(2, 10, device="cuda")
+    z = torch.rand(10, device="cuda")
+    q = torch.rand(2, 7, device="cuda")
+    out = torch.full((7,), 123.0, device="cuda")
+    kw = dict(k=3, alpha_levels=(1, 2, 3, 4, 5), R_min=0.0, R_max=2.0, area=1.0)
+    kw.update(bad)
+    with pytest.raises(aidw.AidwError) as ei:
+        ctx.interpolate(d, z, q, kw.pop("k"), out=out, **kw)
+    assert ei.value.status == aidw.AIDW_EINVAL
+    torch.cuda.synchronize()
+    assert torch.all(out == 123.0)
+
+
+def test_plain_c_entry_point(ctx, torch):
+    inst = workloads.uniform_small(m=500, n=64, seed=8, dtype=np.float32)
+    data_xy, data_z, query_xy = aidw.to_device(inst)
+    out = torch.empty(inst.n, device="cuda")
+    ctx.bind_current_stream()
+    aidw.check(aidw.aidw_interpolate(ctx.h, data_xy.data_ptr(), data_z.data_ptr(), inst.m,
+                                     query_xy.data_ptr(), inst.n, inst.k, inst.levels,
+                                     inst.R_min, inst.R_max, inst.area, out.data_ptr()))
+    o, scale = ref(inst)
+    assert rel_err(out.cpu().numpy(), o, scale).max() <= TOL_F32
+
+
+# ---- determinism and invariance ------------------------------------------------
+
+def test_repeat_runs_are_bitwise_identical(ctx, torch):
+    inst = workloads.clustered(m=20000, n=5000, seed=9)
+    a = gpu_run(ctx, torch, inst)
+    for _ in range(3):
+        assert np.array_equal(a, gpu_run(ctx, torch, inst))
+
+
+def test_query_permutation_permutes_output(ctx, torch):
+    inst = workloads.paper_scale(m=5000, n=3000, seed=10)
+    a = gpu_run(ctx, torch, inst)
+    perm = np.random.default_rng(1).permutation(inst.n)
+    b = gpu_run(ctx, torch, inst, query_index=perm)
+    assert np.array_equal(a[perm], b)
+
+
+def test_async_on_side_stream(ctx, torch):
+    inst = workloads.paper_scale(m=4000, n=4000, seed=11)
+    data_xy, data_z, query_xy = aidw.to_device(inst)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        out = ctx.interpolate(data_xy, data_z, query_xy, inst.k, area=inst.area,
+                              flags=aidw.AIDW_FLAG_ASYNC)
+    s.synchronize()
+    o, scale = ref(inst, idx=np.arange(0, inst.n, 50))
+    assert rel_err(out.cpu().numpy()[::50], o, scale).max() <= TOL_F32
+
+
+# ---- full sizes, sampled ----------------------------------------------------
+
+def test_paper_scale_full_size_sampled(ctx, torch):
+    inst = workloads.paper_scale()  # m = n = 2^20, k = 15, FP32
+    say("paper scale: m=%d n=%d" % (inst.m, inst.n))
+    out = gpu_run(ctx, torch, inst)
+    idx = np.sort(np.random.default_rng(12).choice(inst.n, 160, replace=False))
+    idx = np.concatenate([idx, [0, inst.n - 1]])
+    o, scale = ref(inst, idx=idx)
+    err = rel_err(out[idx], o, scale)
+    say("paper scale fp32: max err %.3e over %d sampled queries" % (err.max(), len(idx)))
+    assert err.max() <= TOL_F32
+
+
+def test_paper_scale_fp64_kernel_subset(ctx, torch):
+    inst = workloads.paper_scale(dtype=np.float64)
+    idx = np.arange(0, inst.n, 256)  # 4096 queries against all 2^20 data points
+    out, r_obs, alpha, knn = gpu_run(ctx, torch, inst, diag=True, query_index=idx)
+    sub = np.arange(0, len(idx), 64)
+    (o, o_r, o_a, o_knn), scale = ref(inst, idx=idx[sub], diag=True)
+    assert np.array_equal(knn[sub].astype(np.int64), o_knn)
+    assert rel_err(out[sub], o, scale).max() <= TOL_F64
+
+
+def test_clustered_full_size_sampled(ctx, torch):
+    inst = workloads.clustered()  # m = n = 2^18, k = 10, FP32, 1% on-point queries
+    out = gpu_run(ctx, torch, inst)
+    on = inst.meta["on_point_queries"]
+    idx = np.sort(np.concatenate([np.random.default_rng(13).choice(inst.n, 120, replace=False),
+                                  on[:40]]))
+    o, scale = ref(inst, idx=idx)
+    err = rel_err(out[idx], o, scale)
+    say("clustered fp32: max err %.3e over %d sampled queries" % (err.max(), len(idx)))
+    assert err.max() <= TOL_F32
+    # an on-point query with a unique location returns that point's value
+    xs = inst.data_x[inst.meta["on_point_data"][:40]]
+    ys = inst.data_y[inst.meta["on_point_data"][:40]]
+    for q, x, y, d in zip(on[:40], xs, ys, inst.meta["on_point_data"][:40]):
+        if np.count_nonzero((inst.data_x == x) & (inst.data_y == y)) == 1:
+            assert out[q] == inst.data_z[d]
