@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--fp64", action="store_true", help="also time the plain FP64 kernel once")
     ap.add_argument("--check", type=int, default=64,
                     help="queries checked against the oracle after timing (0 = none)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 256 MiB device copy, the reference for HBM counters")
     return ap.parse_args()
 
 
@@ -63,6 +65,13 @@ def main():
     def step():
         ctx.interpolate(data_xy, data_z, query_xy, inst.k, inst.levels, inst.R_min, inst.R_max,
                         inst.area, flags=aidw.AIDW_FLAG_ASYNC, out=out)
+
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         step()

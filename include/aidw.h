@@ -132,11 +132,48 @@ aidw_status aidw_interpolate(aidw_t h, const void* data_xy, const void* data_z, 
  * diagnostics (r_obs, alpha, kNN indices) and flags. */
 aidw_status aidw_interpolate_ex(aidw_t h, const aidw_problem* p);
 
-/* Fix the launch shape used for FP32-scaled problems: each lane owns
- * q_per_lane queries (1, 2 or 4).  0 restores the automatic choice, which
- * depends on n and the device's compute-unit count.  Returns AIDW_EINVAL for
- * other values. */
-aidw_status aidw_set_tuning(aidw_t h, int q_per_lane);
+/* Launch shape of the FP32-scaled kernels.  Zero fields mean "automatic". */
+typedef struct aidw_tuning {
+    int q_per_lane;          /* queries owned by each lane: 1, 2 or 4 */
+    int max_waves_per_simd;  /* cap on resident waves per SIMD (1..8), enforced by
+                                reserving LDS per workgroup */
+    int split_segments;      /* split the m data points into this many segments
+                                processed in parallel (1: never split); for
+                                problems with too few queries to fill the GPU */
+} aidw_tuning;
+
+/* Fix the launch shape used for FP32-scaled problems (NULL restores the
+ * automatic choice).  Returns AIDW_EINVAL for values outside the ranges
+ * above. */
+aidw_status aidw_set_tuning(aidw_t h, const aidw_tuning* t);
+
+/* ---- Batches: many independent problems in one launch ----------------------
+ * Every problem must be AIDW_FP32_SCALED and may not request knn_idx.  The
+ * (problem, 64-query tile) work items are ordered longest-first (by m) and
+ * claimed by the waves of one fixed-size grid through an atomic counter,
+ * so problems of very uneven size share the GPU.  Results per query are
+ * bit-identical to aidw_interpolate_ex on the same problem with
+ * q_per_lane = 1 and no split. */
+typedef struct aidw_batch* aidw_batch_t;
+
+/* Validate the problems, upload the work list and capture the launch as a
+ * hipGraph.  The problems' device buffers must stay valid while the batch
+ * exists; their contents may change between launches.  On error nothing is
+ * kept and aidw_last_error() names the offending problem. */
+aidw_status aidw_batch_create(aidw_t h, const aidw_problem* problems, int count,
+                              aidw_batch_t* out);
+
+/* Replay the captured graph on the handle's current stream (synchronous
+ * unless flags has AIDW_FLAG_ASYNC).  Launches of one batch must not
+ * overlap: they share the batch's claim counter. */
+aidw_status aidw_batch_launch(aidw_batch_t b, unsigned flags);
+
+/* Free the batch's device memory and graph (waits for the handle's stream). */
+void aidw_batch_destroy(aidw_batch_t b);
+
+/* One-shot batch: build, launch once, wait, free. */
+aidw_status aidw_interpolate_batch(aidw_t h, const aidw_problem* problems, int count,
+                                   unsigned flags);
 
 /* Wait until all work issued on the handle's stream has finished. */
 aidw_status aidw_synchronize(aidw_t h);

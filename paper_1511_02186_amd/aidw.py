@@ -54,6 +54,11 @@ class aidw_problem(ctypes.Structure):
     ]
 
 
+class aidw_tuning(ctypes.Structure):
+    _fields_ = [("q_per_lane", ctypes.c_int), ("max_waves_per_simd", ctypes.c_int),
+                ("split_segments", ctypes.c_int)]
+
+
 class AidwError(RuntimeError):
     def __init__(self, status, message):
         super().__init__("%s: %s" % (status_name(status), message))
@@ -72,8 +77,14 @@ _SIGNATURES = {
                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_void_p]),
     "aidw_interpolate_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem)]),
-    "aidw_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "aidw_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_tuning)]),
     "aidw_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
+    "aidw_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem), ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "aidw_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint]),
+    "aidw_batch_destroy": (None, [ctypes.c_void_p]),
+    "aidw_interpolate_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem),
+                                              ctypes.c_int, ctypes.c_uint]),
     "aidw_last_error": (ctypes.c_char_p, []),
     "aidw_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "aidw_version": (ctypes.c_int, []),
@@ -138,8 +149,37 @@ def aidw_interpolate_ex(h, problem: aidw_problem) -> int:
     return lib().aidw_interpolate_ex(h, ctypes.byref(problem))
 
 
-def aidw_set_tuning(h, q_per_lane: int) -> int:
-    return lib().aidw_set_tuning(h, int(q_per_lane))
+def aidw_set_tuning(h, q_per_lane: int = 0, max_waves_per_simd: int = 0,
+                    split_segments: int = 0) -> int:
+    if not q_per_lane and not max_waves_per_simd and not split_segments:
+        return lib().aidw_set_tuning(h, None)
+    t = aidw_tuning(int(q_per_lane), int(max_waves_per_simd), int(split_segments))
+    return lib().aidw_set_tuning(h, ctypes.byref(t))
+
+
+def _problem_array(problems):
+    arr = (aidw_problem * len(problems))(*problems)
+    return arr
+
+
+def aidw_batch_create(h, problems) -> int:
+    arr = _problem_array(problems)
+    b = ctypes.c_void_p()
+    check(lib().aidw_batch_create(h, arr, len(problems), ctypes.byref(b)))
+    return b.value
+
+
+def aidw_batch_launch(b, flags: int = 0) -> int:
+    return lib().aidw_batch_launch(b, int(flags))
+
+
+def aidw_batch_destroy(b) -> None:
+    lib().aidw_batch_destroy(b)
+
+
+def aidw_interpolate_batch(h, problems, flags: int = 0) -> int:
+    arr = _problem_array(problems)
+    return lib().aidw_interpolate_batch(h, arr, len(problems), int(flags))
 
 
 def aidw_synchronize(h) -> int:
@@ -177,8 +217,9 @@ class Context:
         except Exception:
             pass
 
-    def set_tuning(self, q_per_lane: int = 0):
-        check(aidw_set_tuning(self.h, q_per_lane))
+    def set_tuning(self, q_per_lane: int = 0, max_waves_per_simd: int = 0,
+                   split_segments: int = 0):
+        check(aidw_set_tuning(self.h, q_per_lane, max_waves_per_simd, split_segments))
 
     def bind_current_stream(self):
         import torch

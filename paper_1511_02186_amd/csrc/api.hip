@@ -5,6 +5,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
+#include <vector>
 #include <new>
 #include <string>
 
@@ -35,10 +37,24 @@ aidw_status hip_fail(hipError_t e, const char* what) {
 struct aidw_ctx {
     int device = 0;
     aidw_precision default_precision = AIDW_FP32_SCALED;
-    size_t hbm_budget = 0;
+    size_t hbm_budget = 0;       // 0: unlimited
+    size_t hbm_in_use = 0;       // library-owned device bytes
     hipStream_t stream = nullptr;
     int cu_count = 0;
-    int q_per_lane = 0;  // 0: automatic
+    aidw_tuning tuning{0, 0, 0};  // zero fields: automatic
+    void* workspace = nullptr;    // split-m scratch, grown on demand
+    size_t workspace_bytes = 0;
+};
+
+struct aidw_batch {
+    aidw_t h = nullptr;
+    int count = 0;
+    aidw::BatchLaunch launch{};
+    void* device_block = nullptr;  // problems, items and counter
+    size_t device_bytes = 0;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace aidw {
@@ -93,12 +109,93 @@ aidw::AlphaParams alpha_params(const aidw_problem* p) {
     return ap;
 }
 
-int default_q_per_lane(const aidw_ctx* h, int64_t n) {
-    // Keep at least ~4 waves per SIMD in flight before giving lanes more queries.
-    const int64_t simds = (int64_t)(h->cu_count > 0 ? h->cu_count : 256) * 4;
-    if (n >= simds * 4 * aidw::kWaveSize * 4) return 4;
-    if (n >= simds * 4 * aidw::kWaveSize * 2) return 2;
+int default_q_per_lane(const aidw_ctx*, int64_t) {
+    // One query per lane: the lean register footprint (about 60 VGPRs) keeps
+    // 8 waves per SIMD resident, which hides the scalar-load and
+    // transcendental latencies better than more queries per lane did on
+    // MI355X at every size measured.
     return 1;
+}
+
+// Library-owned device allocations are counted against the handle's budget.
+aidw_status device_alloc(aidw_t h, size_t bytes, void** out) {
+    *out = nullptr;
+    if (bytes == 0) return AIDW_OK;
+    if (h->hbm_budget && h->hbm_in_use + bytes > h->hbm_budget)
+        return fail(AIDW_ENOMEM, "device budget exceeded: %zu in use + %zu requested > %zu",
+                    h->hbm_in_use, bytes, h->hbm_budget);
+    hipError_t e = hipMalloc(out, bytes);
+    if (e != hipSuccess) {
+        *out = nullptr;
+        return fail(AIDW_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    h->hbm_in_use += bytes;
+    return AIDW_OK;
+}
+
+void device_free(aidw_t h, void* p, size_t bytes) {
+    if (!p) return;
+    (void)hipFree(p);
+    h->hbm_in_use -= bytes;
+}
+
+aidw_status ensure_workspace(aidw_t h, size_t bytes) {
+    if (bytes <= h->workspace_bytes) return AIDW_OK;
+    hipError_t e = hipStreamSynchronize(h->stream);  // the old buffer may still be in use
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    device_free(h, h->workspace, h->workspace_bytes);
+    h->workspace = nullptr;
+    h->workspace_bytes = 0;
+    aidw_status st = device_alloc(h, bytes, &h->workspace);
+    if (st == AIDW_OK) h->workspace_bytes = bytes;
+    return st;
+}
+
+// Number of data segments for an FP32-scaled problem: enough (tile, segment)
+// waves to give every SIMD about 8 resident waves, with segments of at least
+// kMinSegment points.  1 means the fused kernel.
+constexpr int kMinSegment = 2048;
+
+aidw::SplitPlan split_plan(const aidw_ctx* h, int64_t m, int64_t n) {
+    aidw::SplitPlan sp{1, (int)m, (int)((n + aidw::kWaveSize - 1) / aidw::kWaveSize)};
+    int want = h->tuning.split_segments;
+    if (want == 0) {
+        const int64_t target = (int64_t)(h->cu_count > 0 ? h->cu_count : 256) * 4 * 8;
+        if (sp.tiles >= target) return sp;
+        want = (int)std::min<int64_t>((target + sp.tiles - 1) / sp.tiles, 1 << 20);
+    }
+    int64_t seg = (m + want - 1) / want;
+    if (h->tuning.split_segments == 0) seg = std::max<int64_t>(seg, kMinSegment);
+    seg = (seg + 31) / 32 * 32;  // whole scalar-load batches
+    if (seg >= m) return sp;
+    sp.seg_len = (int)seg;
+    sp.segments = (int)((m + seg - 1) / seg);
+    return sp;
+}
+
+size_t split_workspace_bytes(const aidw::SplitPlan& sp, int K, int64_t n, aidw::SplitWorkspace* ws,
+                             char* base) {
+    const size_t part = (size_t)sp.segments * K * n * sizeof(float);
+    const size_t qpar = 2 * (size_t)n * sizeof(float);
+    const size_t psum = (size_t)sp.segments * 2 * n * sizeof(double);
+    const size_t a = 256;
+    const size_t o_qpar = (part + a - 1) / a * a;
+    const size_t o_psum = (o_qpar + qpar + a - 1) / a * a;
+    if (ws) {
+        ws->part = reinterpret_cast<float*>(base);
+        ws->qpar = reinterpret_cast<float*>(base + o_qpar);
+        ws->psum = reinterpret_cast<double*>(base + o_psum);
+    }
+    return o_psum + psum;
+}
+
+aidw::ProblemF32 problem_f32(const aidw_problem* p) {
+    const int m = (int)p->m, n = (int)p->n;
+    const float* xy = static_cast<const float*>(p->data_xy);
+    const float* qxy = static_cast<const float*>(p->query_xy);
+    return aidw::ProblemF32{xy, xy + m, static_cast<const float*>(p->data_z), qxy, qxy + n,
+                            static_cast<float*>(p->out), p->r_obs, p->alpha, p->knn_idx, m, n,
+                            alpha_params(p)};
 }
 
 aidw_status run_problem(aidw_t h, const aidw_problem* p) {
@@ -109,12 +206,19 @@ aidw_status run_problem(aidw_t h, const aidw_problem* p) {
     hipError_t e;
     const int m = (int)p->m, n = (int)p->n;
     if (p->precision == AIDW_FP32_SCALED) {
-        const float* xy = static_cast<const float*>(p->data_xy);
-        const float* qxy = static_cast<const float*>(p->query_xy);
-        aidw::ProblemF32 q{xy, xy + m, static_cast<const float*>(p->data_z), qxy, qxy + n,
-                           static_cast<float*>(p->out), p->r_obs, p->alpha, p->knn_idx, m, n, ap};
-        aidw::LaunchF32 cfg{h->q_per_lane ? h->q_per_lane : default_q_per_lane(h, n)};
-        e = aidw::launch_aidw_f32(q, cfg, h->stream);
+        const aidw::ProblemF32 q = problem_f32(p);
+        aidw::LaunchF32 cfg{h->tuning.q_per_lane ? h->tuning.q_per_lane : default_q_per_lane(h, n),
+                            h->tuning.max_waves_per_simd};
+        aidw::SplitPlan sp{1, m, 0};
+        aidw::SplitWorkspace ws{};
+        if (!p->knn_idx) sp = split_plan(h, m, n);
+        if (sp.segments > 1) {
+            const int K = aidw::k_bucket(p->k);
+            aidw_status st = ensure_workspace(h, split_workspace_bytes(sp, K, n, nullptr, nullptr));
+            if (st != AIDW_OK) return st;
+            split_workspace_bytes(sp, K, n, &ws, static_cast<char*>(h->workspace));
+        }
+        e = aidw::launch_aidw_f32(q, cfg, &sp, &ws, h->stream);
     } else {
         const double* xy = static_cast<const double*>(p->data_xy);
         const double* qxy = static_cast<const double*>(p->query_xy);
@@ -164,12 +268,19 @@ void aidw_destroy(aidw_t h) {
     if (!h) return;
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
+    device_free(h, h->workspace, h->workspace_bytes);
     delete h;
 }
 
 aidw_status aidw_set_stream(aidw_t h, void* stream) {
     if (!h) return fail(AIDW_EINVAL, "handle is NULL");
-    h->stream = static_cast<hipStream_t>(stream);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (s != h->stream) {
+        // library-owned scratch is reused by the next call: let the old stream drain
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        h->stream = s;
+    }
     return AIDW_OK;
 }
 
@@ -201,11 +312,18 @@ aidw_status aidw_interpolate_ex(aidw_t h, const aidw_problem* p) {
     return run_problem(h, p);
 }
 
-aidw_status aidw_set_tuning(aidw_t h, int q_per_lane) {
+aidw_status aidw_set_tuning(aidw_t h, const aidw_tuning* t) {
     if (!h) return fail(AIDW_EINVAL, "handle is NULL");
-    if (q_per_lane != 0 && q_per_lane != 1 && q_per_lane != 2 && q_per_lane != 4)
+    if (!t) {
+        h->tuning = aidw_tuning{0, 0, 0};
+        return AIDW_OK;
+    }
+    if (t->split_segments < 0) return fail(AIDW_EINVAL, "split_segments must be >= 0");
+    if (t->q_per_lane != 0 && t->q_per_lane != 1 && t->q_per_lane != 2 && t->q_per_lane != 4)
         return fail(AIDW_EINVAL, "q_per_lane must be 0, 1, 2 or 4");
-    h->q_per_lane = q_per_lane;
+    if (t->max_waves_per_simd < 0 || t->max_waves_per_simd > 8)
+        return fail(AIDW_EINVAL, "max_waves_per_simd must be in [0, 8]");
+    h->tuning = *t;
     return AIDW_OK;
 }
 
@@ -230,5 +348,148 @@ const char* aidw_status_string(aidw_status s) {
 }
 
 int aidw_version(void) { return (AIDW_VERSION_MAJOR << 16) | AIDW_VERSION_MINOR; }
+
+}  // extern "C"
+
+// ---- batched problems ------------------------------------------------------------
+
+namespace {
+
+aidw_status batch_build(aidw_t h, const aidw_problem* problems, int count, aidw_batch* b) {
+    if (count < 0) return fail(AIDW_EINVAL, "count = %d < 0", count);
+    if (count > 0 && !problems) return fail(AIDW_EINVAL, "problems is NULL");
+    std::vector<aidw::ProblemF32> probs((size_t)count);
+    std::vector<aidw::BatchItem> items;
+    int kmax = 1;
+    for (int i = 0; i < count; ++i) {
+        const aidw_problem* p = &problems[i];
+        aidw_status st = validate(p);
+        if (st != AIDW_OK)
+            return fail(st, "problem %d: %s", i, aidw_last_error());
+        if (p->precision != AIDW_FP32_SCALED)
+            return fail(AIDW_EINVAL, "problem %d: batched problems must be AIDW_FP32_SCALED", i);
+        if (p->knn_idx)
+            return fail(AIDW_EINVAL, "problem %d: knn_idx is not produced by batched launches", i);
+        probs[i] = problem_f32(p);
+        kmax = std::max(kmax, p->k);
+        for (int64_t base = 0; base < p->n; base += aidw::kWaveSize)
+            items.push_back(aidw::BatchItem{i, (int)base});
+    }
+    if (items.size() > (size_t)INT32_MAX) return fail(AIDW_EINVAL, "too many query tiles");
+    // Longest first: an item's cost is proportional to its problem's m.
+    std::stable_sort(items.begin(), items.end(),
+                     [&](const aidw::BatchItem& x, const aidw::BatchItem& y) {
+                         return probs[x.problem].m > probs[y.problem].m;
+                     });
+    const size_t a = 256;
+    const size_t sz_p = (sizeof(aidw::ProblemF32) * probs.size() + a - 1) / a * a;
+    const size_t sz_i = (sizeof(aidw::BatchItem) * items.size() + a - 1) / a * a;
+    const size_t bytes = sz_p + sz_i + a;
+    aidw_status st = device_alloc(h, bytes, &b->device_block);
+    if (st != AIDW_OK) return st;
+    b->device_bytes = bytes;
+    char* base = static_cast<char*>(b->device_block);
+    hipError_t e = hipMemcpy(base, probs.data(), sizeof(aidw::ProblemF32) * probs.size(),
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess && !items.empty())
+        e = hipMemcpy(base + sz_p, items.data(), sizeof(aidw::BatchItem) * items.size(),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    b->h = h;
+    b->count = count;
+    b->launch.problems = reinterpret_cast<const aidw::ProblemF32*>(base);
+    b->launch.items = reinterpret_cast<const aidw::BatchItem*>(base + sz_p);
+    b->launch.counter = reinterpret_cast<int*>(base + sz_p + sz_i);
+    b->launch.n_items = (int)items.size();
+    b->launch.K = aidw::k_bucket(kmax);
+    int per_cu = aidw::batch_blocks_per_cu(b->launch.K);
+    if (per_cu <= 0) per_cu = 2;
+    const int64_t groups_needed = ((int64_t)items.size() + aidw::kWavesPerGroup - 1) / aidw::kWavesPerGroup;
+    b->launch.groups = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * h->cu_count,
+                                                                     groups_needed));
+    return AIDW_OK;
+}
+
+void batch_release(aidw_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    if (b->h) device_free(b->h, b->device_block, b->device_bytes);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->capture_stream = nullptr;
+    b->device_block = nullptr;
+}
+
+aidw_status batch_capture(aidw_batch* b) {
+    hipError_t e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+    e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le = aidw::launch_aidw_f32_batch(b->launch, b->capture_stream);
+    e = hipStreamEndCapture(b->capture_stream, &b->graph);
+    if (le != hipSuccess) return hip_fail(le, "batched launch during capture");
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    return AIDW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+aidw_status aidw_batch_create(aidw_t h, const aidw_problem* problems, int count,
+                              aidw_batch_t* out) {
+    if (!h || !out) return fail(AIDW_EINVAL, "handle or out is NULL");
+    *out = nullptr;
+    aidw_batch* b = new (std::nothrow) aidw_batch;
+    if (!b) return fail(AIDW_ENOMEM, "host allocation failed");
+    aidw_status st = batch_build(h, problems, count, b);
+    if (st == AIDW_OK && b->launch.n_items > 0) st = batch_capture(b);
+    if (st != AIDW_OK) {
+        batch_release(b);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return AIDW_OK;
+}
+
+aidw_status aidw_batch_launch(aidw_batch_t b, unsigned flags) {
+    if (!b) return fail(AIDW_EINVAL, "batch is NULL");
+    if (b->launch.n_items == 0) return AIDW_OK;
+    hipError_t e = hipGraphLaunch(b->exec, b->h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    if (!(flags & AIDW_FLAG_ASYNC)) {
+        e = hipStreamSynchronize(b->h->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    }
+    return AIDW_OK;
+}
+
+void aidw_batch_destroy(aidw_batch_t b) {
+    if (!b) return;
+    if (b->h) (void)hipStreamSynchronize(b->h->stream);
+    batch_release(b);
+    delete b;
+}
+
+aidw_status aidw_interpolate_batch(aidw_t h, const aidw_problem* problems, int count,
+                                   unsigned flags) {
+    if (!h) return fail(AIDW_EINVAL, "handle is NULL");
+    aidw_batch b;
+    aidw_status st = batch_build(h, problems, count, &b);
+    if (st == AIDW_OK && b.launch.n_items > 0) {
+        hipError_t e = aidw::launch_aidw_f32_batch(b.launch, h->stream);
+        if (e != hipSuccess) st = hip_fail(e, "batched launch");
+        // the work list lives until the launch completes
+        hipError_t se = hipStreamSynchronize(h->stream);
+        if (st == AIDW_OK && se != hipSuccess) st = hip_fail(se, "hipStreamSynchronize");
+    }
+    (void)flags;
+    batch_release(&b);
+    return st;
+}
 
 }  // extern "C"

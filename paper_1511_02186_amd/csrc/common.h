@@ -59,10 +59,52 @@ int k_bucket(int k);
 
 // Launch configuration of the FP32-scaled fused kernel.
 struct LaunchF32 {
-    int q_per_lane;  // queries owned by each lane: 1, 2 or 4
+    int q_per_lane;          // queries owned by each lane: 1, 2 or 4
+    int max_waves_per_simd;  // 0: no cap; else LDS is reserved so that at most
+                             // this many workgroups (one wave per SIMD each) share a CU
 };
 
-hipError_t launch_aidw_f32(const ProblemF32& p, const LaunchF32& cfg, hipStream_t stream);
+// LDS per compute unit on gfx950.
+constexpr int kLdsPerCU = 160 * 1024;
+
+// Split of the m data points into `segments` contiguous ranges of `seg_len`
+// points (the last may be shorter), for problems with too few queries to
+// fill the device.  tiles = ceil(n / 64).
+struct SplitPlan {
+    int segments;
+    int seg_len;
+    int tiles;
+};
+
+// Device workspace of a split launch (sizes in split_workspace_bytes).
+struct SplitWorkspace {
+    float* part;   // [segments][K][n] per-segment k-nearest lists
+    float* qpar;   // [2][n] pass-2 exponent terms per query
+    double* psum;  // [segments][2][n] per-segment sum w and sum w z
+};
+
+// One unit of batched work: 64 consecutive queries of one problem.
+struct BatchItem {
+    int problem;
+    int base;  // first query of the tile
+};
+
+// A batched launch: `groups` workgroups of kGroupSize threads whose waves
+// claim items[0..n_items) through `counter` (reset by the launch itself).
+struct BatchLaunch {
+    const ProblemF32* problems;  // device array
+    const BatchItem* items;      // device array, longest first
+    int* counter;                // device int
+    int n_items;
+    int groups;
+    int K;                       // register bucket >= every problem's k
+};
+
+hipError_t launch_aidw_f32(const ProblemF32& p, const LaunchF32& cfg, const SplitPlan* sp,
+                           const SplitWorkspace* ws, hipStream_t stream);
+hipError_t launch_aidw_f32_batch(const BatchLaunch& b, hipStream_t stream);
+// Resident workgroups per CU of the batched kernel for register bucket K.
+int batch_blocks_per_cu(int K);
 hipError_t launch_aidw_f64(const ProblemF64& p, hipStream_t stream);
 
 }  // namespace aidw

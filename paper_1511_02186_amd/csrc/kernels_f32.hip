@@ -1,13 +1,12 @@
-// FP32-scaled fused AIDW kernel for gfx950.
+// FP32-scaled AIDW kernels for gfx950.
 //
-// One launch runs both of the paper's full passes over the m data points
-// for every query (Sec. 3.2): pass 1 finds the k nearest data points
-// (Sec. 3.1.2) and from them alpha (Eq. 2-6); pass 2 forms the weighted
-// average of Eq. 1.
+// Every query gets the paper's two full passes over the m data points
+// (Sec. 3.2): pass 1 finds the k nearest data points (Sec. 3.1.2) and from
+// them alpha (Eq. 2-6); pass 2 forms the weighted average of Eq. 1.
 //
 // Mapping to CDNA4:
-//  * Each lane owns Q queries (query = wave*64*Q + slot*64 + lane), so query
-//    loads and output stores are coalesced per slot.
+//  * A wave owns a tile of 64*Q queries; lane l, slot s holds query
+//    base + s*64 + l, so query loads and output stores are coalesced.
 //  * All lanes of a wave walk the data points in the same order, so a data
 //    point is wave-uniform: its coordinates are fetched with scalar loads
 //    into SGPRs (B points per batch) and broadcast to every lane as an
@@ -31,13 +30,36 @@
 //    points, the clamp maps it to 0 (weight 1), and every other point gets
 //    weight exp2(-inf) = 0, so the result is the mean z of the coincident
 //    points.
+//
+// Three drivers share these building blocks:
+//  * aidw_f32_fused: one wave per tile, both passes over all m points;
+//  * aidw_f32_batch: a fixed-size grid whose waves claim (problem, tile)
+//    items from a longest-first work list through an atomic counter, so one
+//    launch (capturable in a hipGraph) serves many problems of uneven size;
+//  * split-m: when n is too small to fill the device, the m points are cut
+//    into S segments; one launch computes per-segment k-nearest lists, a
+//    merge kernel turns them into alpha, a third launch computes
+//    per-segment weighted sums and a last kernel adds the segments in order.
 #include "common.h"
 #include "device_math.h"
 
 namespace aidw {
 namespace {
 
-constexpr int kBatch = 16;
+// Data points per scalar-load batch.  Pass 1 loads x and y (2 SGPRs per
+// point), pass 2 also z (3 SGPRs per point); the batch is sized so that the
+// SGPR file holds it without spills.  Lanes that own several queries use
+// smaller batches to leave SGPRs for their extra state.
+#ifndef AIDW_F32_B1
+#define AIDW_F32_B1 32
+#endif
+#ifndef AIDW_F32_B2
+#define AIDW_F32_B2 16
+#endif
+template <int Q>
+constexpr int batch1_for() { return Q == 1 ? AIDW_F32_B1 : 16; }
+template <int Q>
+constexpr int batch2_for() { return Q == 1 ? AIDW_F32_B2 : 16; }
 
 __device__ __forceinline__ float sqdist(float qx, float qy, float px, float py) {
     const float ex = qx - px;
@@ -45,17 +67,120 @@ __device__ __forceinline__ float sqdist(float qx, float qy, float px, float py) 
     return fmaf(ey, ey, ex * ex);
 }
 
-template <int Q, bool SAFE>
-__device__ __forceinline__ void pass2(const float* __restrict__ X, const float* __restrict__ Y,
-                                      const float* __restrict__ Z, int m, const float (&qx)[Q],
-                                      const float (&qy)[Q], const float (&na)[Q],
-                                      const float (&aL0)[Q], double (&Sw)[Q], double (&Swz)[Q]) {
-    const int mb = m - m % kBatch;
-    int j = 0;
-    for (; j < mb; j += kBatch) {
-        float px[kBatch], py[kBatch], pz[kBatch];
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWaveSize - 1); }
+
+// Global wave index, made visibly wave-uniform (an SGPR) so that everything
+// derived from it -- data ranges in particular -- stays scalar.
+__device__ __forceinline__ int wave_id() {
+    return __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6));
+}
+
+// Data points are read through the constant address space: the kernels never
+// write them, and loads from that space at wave-uniform addresses are always
+// lowered to scalar loads, also when the array's address itself was loaded
+// from memory (a batch descriptor).
+typedef const __attribute__((address_space(4))) float* cptr;
+__device__ __forceinline__ cptr as_const(const float* p) { return (cptr)p; }
+
+// ---- pass 1: fold data points [j0, j1) into the k-nearest lists ------------
+template <int K, int Q, bool TRACK>
+__device__ __forceinline__ void scan_knn(cptr X, cptr Y, int j0, int j1, const float (&qx)[Q],
+                                         const float (&qy)[Q], float (&top)[Q][K],
+                                         int (&tix)[TRACK ? Q : 1][TRACK ? K : 1]) {
+    constexpr int B = batch1_for<Q>();
+    int j = j0;
+    for (; j + B <= j1; j += B) {
+        float px[B], py[B];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
+        for (int u = 0; u < B; ++u) {
+            px[u] = X[j + u];
+            py[u] = Y[j + u];
+        }
+        float d2[Q][B];
+        float mn[Q];
+        bool hit = false;
+#pragma unroll
+        for (int s = 0; s < Q; ++s) {
+#pragma unroll
+            for (int u = 0; u < B; ++u) d2[s][u] = sqdist(qx[s], qy[s], px[u], py[u]);
+            mn[s] = d2[s][0];
+#pragma unroll
+            for (int u = 1; u < B; ++u) mn[s] = fminf(mn[s], d2[s][u]);
+            hit |= mn[s] < top[s][K - 1];
+        }
+        if (hit) {
+#pragma unroll
+            for (int s = 0; s < Q; ++s) {
+                if (mn[s] < top[s][K - 1]) {
+#pragma unroll
+                    for (int u = 0; u < B; ++u) {
+                        if (d2[s][u] < top[s][K - 1]) {
+                            if constexpr (TRACK)
+                                list_insert_idx<K, float>(top[s], tix[s], d2[s][u], j + u);
+                            else
+                                list_insert<K>(top[s], d2[s][u]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    for (; j < j1; ++j) {
+        const float px = X[j], py = Y[j];
+#pragma unroll
+        for (int s = 0; s < Q; ++s) {
+            const float d2 = sqdist(qx[s], qy[s], px, py);
+            if (d2 < top[s][K - 1]) {
+                if constexpr (TRACK)
+                    list_insert_idx<K, float>(top[s], tix[s], d2, j);
+                else
+                    list_insert<K>(top[s], d2);
+            }
+        }
+    }
+}
+
+template <int K, int Q, bool TRACK>
+__device__ __forceinline__ void init_lists(float (&top)[Q][K],
+                                           int (&tix)[TRACK ? Q : 1][TRACK ? K : 1], int k) {
+    const int pad = K - k;
+#pragma unroll
+    for (int s = 0; s < Q; ++s)
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            top[s][i] = i < pad ? -INFINITY : INFINITY;
+            if constexpr (TRACK) tix[s][i] = -1;
+        }
+}
+
+// alpha of one query (Eq. 2-6) and its pass-2 exponent terms: weights are
+// exp2(na * log2(d^2) + aL0) with na = -alpha/2, aL0 = (alpha/2) log2(d_min^2).
+template <int K>
+__device__ __forceinline__ void query_power(const float (&top)[K], const AlphaParams& ap,
+                                            double& r_obs, double& al, float& na, float& aL0) {
+    al = alpha_from_list<K, float>(top, ap, r_obs);
+    const float a = (float)(0.5 * al);
+    const float L0 = __builtin_amdgcn_logf(list_min<K, float>(top, ap.k));
+    na = -a;
+    aL0 = a * L0;
+}
+
+// True when the query coincides with a data point: log2(d_min^2) = -inf makes
+// aL0 -inf (alpha > 0) or NaN (alpha = 0).
+__device__ __forceinline__ bool coincident(float aL0) { return !(aL0 > -INFINITY); }
+
+// ---- pass 2: weighted sums over data points [j0, j1) -----------------------
+template <int Q, bool SAFE>
+__device__ __forceinline__ void scan_wsum(cptr X, cptr Y, cptr Z, int j0, int j1,
+                                          const float (&qx)[Q], const float (&qy)[Q],
+                                          const float (&na)[Q], const float (&aL0)[Q],
+                                          double (&Sw)[Q], double (&Swz)[Q]) {
+    constexpr int B = batch2_for<Q>();
+    int j = j0;
+    for (; j + B <= j1; j += B) {
+        float px[B], py[B], pz[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
             px[u] = X[j + u];
             py[u] = Y[j + u];
             pz[u] = Z[j + u];
@@ -64,7 +189,7 @@ __device__ __forceinline__ void pass2(const float* __restrict__ X, const float* 
         for (int s = 0; s < Q; ++s) {
             float sw = 0.0f, swz = 0.0f;
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
+            for (int u = 0; u < B; ++u) {
                 const float d2 = sqdist(qx[s], qy[s], px[u], py[u]);
                 float t = fmaf(na[s], __builtin_amdgcn_logf(d2), aL0[s]);
                 if (SAFE) t = fminf(t, 0.0f);
@@ -76,7 +201,7 @@ __device__ __forceinline__ void pass2(const float* __restrict__ X, const float* 
             Swz[s] += (double)swz;
         }
     }
-    for (; j < m; ++j) {
+    for (; j < j1; ++j) {
         const float px = X[j], py = Y[j], pz = Z[j];
 #pragma unroll
         for (int s = 0; s < Q; ++s) {
@@ -90,101 +215,51 @@ __device__ __forceinline__ void pass2(const float* __restrict__ X, const float* 
     }
 }
 
-template <int K, int Q, bool TRACK>
-__global__ __launch_bounds__(kGroupSize) void aidw_f32_fused(ProblemF32 p) {
-    const int lane = threadIdx.x & (kWaveSize - 1);
-    const int wave = blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6);
-    const int m = p.m;
-    const float* __restrict__ X = p.dx;
-    const float* __restrict__ Y = p.dy;
-    const float* __restrict__ Z = p.dz;
+template <int Q>
+__device__ __forceinline__ void scan_wsum_any(cptr X, cptr Y, cptr Z, int j0, int j1,
+                                              const float (&qx)[Q], const float (&qy)[Q],
+                                              const float (&na)[Q], const float (&aL0)[Q],
+                                              double (&Sw)[Q], double (&Swz)[Q]) {
+    bool any_coincident = false;
+#pragma unroll
+    for (int s = 0; s < Q; ++s) any_coincident |= coincident(aL0[s]);
+    if (__any(any_coincident))
+        scan_wsum<Q, true>(X, Y, Z, j0, j1, qx, qy, na, aL0, Sw, Swz);
+    else
+        scan_wsum<Q, false>(X, Y, Z, j0, j1, qx, qy, na, aL0, Sw, Swz);
+}
 
-    int qi[Q];
-    float qx[Q], qy[Q];
+template <int Q>
+__device__ __forceinline__ void load_queries(const ProblemF32& p, int base, int (&qi)[Q],
+                                             float (&qx)[Q], float (&qy)[Q]) {
+    const int lane = lane_id();
 #pragma unroll
     for (int s = 0; s < Q; ++s) {
-        qi[s] = (wave * Q + s) * kWaveSize + lane;
+        qi[s] = base + s * kWaveSize + lane;
         const int c = qi[s] < p.n ? qi[s] : p.n - 1;
         qx[s] = p.qx[c];
         qy[s] = p.qy[c];
     }
+}
 
-    // ---- pass 1: k nearest data points by squared distance -----------------
-    const int pad = K - p.ap.k;
+// ---- one tile of 64*Q queries, both passes over all m points ---------------
+template <int K, int Q, bool TRACK>
+__device__ __forceinline__ void fused_tile(const ProblemF32& p, int base) {
+    int qi[Q];
+    float qx[Q], qy[Q];
+    load_queries<Q>(p, base, qi, qx, qy);
+
     float top[Q][K];
     int tix[TRACK ? Q : 1][TRACK ? K : 1];
-#pragma unroll
-    for (int s = 0; s < Q; ++s)
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-            top[s][i] = i < pad ? -INFINITY : INFINITY;
-            if constexpr (TRACK) tix[s][i] = -1;
-        }
+    init_lists<K, Q, TRACK>(top, tix, p.ap.k);
+    scan_knn<K, Q, TRACK>(as_const(p.dx), as_const(p.dy), 0, p.m, qx, qy, top, tix);
 
-    const int mb = m - m % kBatch;
-    int j = 0;
-    for (; j < mb; j += kBatch) {
-        float px[kBatch], py[kBatch];
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            px[u] = X[j + u];
-            py[u] = Y[j + u];
-        }
-        float d2[Q][kBatch];
-        float mn[Q];
-        bool hit = false;
-#pragma unroll
-        for (int s = 0; s < Q; ++s) {
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) d2[s][u] = sqdist(qx[s], qy[s], px[u], py[u]);
-            mn[s] = d2[s][0];
-#pragma unroll
-            for (int u = 1; u < kBatch; ++u) mn[s] = fminf(mn[s], d2[s][u]);
-            hit |= mn[s] < top[s][K - 1];
-        }
-        if (hit) {
-#pragma unroll
-            for (int s = 0; s < Q; ++s) {
-                if (mn[s] < top[s][K - 1]) {
-#pragma unroll
-                    for (int u = 0; u < kBatch; ++u) {
-                        if (d2[s][u] < top[s][K - 1]) {
-                            if constexpr (TRACK)
-                                list_insert_idx<K, float>(top[s], tix[s], d2[s][u], j + u);
-                            else
-                                list_insert<K>(top[s], d2[s][u]);
-                        }
-                    }
-                }
-            }
-        }
-    }
-    for (; j < m; ++j) {
-        const float px = X[j], py = Y[j];
-#pragma unroll
-        for (int s = 0; s < Q; ++s) {
-            const float d2 = sqdist(qx[s], qy[s], px, py);
-            if (d2 < top[s][K - 1]) {
-                if constexpr (TRACK)
-                    list_insert_idx<K, float>(top[s], tix[s], d2, j);
-                else
-                    list_insert<K>(top[s], d2);
-            }
-        }
-    }
-
-    // ---- alpha per query (Eq. 2-6) in FP64 ---------------------------------
+    const int pad = K - p.ap.k;
     float na[Q], aL0[Q];
-    bool coincident = false;
 #pragma unroll
     for (int s = 0; s < Q; ++s) {
-        double r_obs;
-        const double al = alpha_from_list<K, float>(top[s], p.ap, r_obs);
-        const float a = (float)(0.5 * al);
-        const float L0 = __builtin_amdgcn_logf(list_min<K, float>(top[s], p.ap.k));
-        na[s] = -a;
-        aL0[s] = a * L0;
-        coincident |= (L0 == -INFINITY);
+        double r_obs, al;
+        query_power<K>(top[s], p.ap, r_obs, al, na[s], aL0[s]);
         if (qi[s] < p.n) {
             if (p.r_obs) p.r_obs[qi[s]] = r_obs;
             if (p.alpha) p.alpha[qi[s]] = al;
@@ -196,14 +271,11 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_fused(ProblemF32 p) {
         }
     }
 
-    // ---- pass 2: weighted average of Eq. 1 with rescaled weights ------------
     double Sw[Q], Swz[Q];
 #pragma unroll
     for (int s = 0; s < Q; ++s) Sw[s] = Swz[s] = 0.0;
-    if (__any(coincident))
-        pass2<Q, true>(X, Y, Z, m, qx, qy, na, aL0, Sw, Swz);
-    else
-        pass2<Q, false>(X, Y, Z, m, qx, qy, na, aL0, Sw, Swz);
+    scan_wsum_any<Q>(as_const(p.dx), as_const(p.dy), as_const(p.dz), 0, p.m, qx, qy, na, aL0, Sw,
+                     Swz);
 
 #pragma unroll
     for (int s = 0; s < Q; ++s)
@@ -211,40 +283,231 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_fused(ProblemF32 p) {
 }
 
 template <int K, int Q, bool TRACK>
-hipError_t launch_kq(const ProblemF32& p, hipStream_t stream) {
-    const int64_t per_group = (int64_t)kGroupSize * Q;
-    const int64_t groups = (p.n + per_group - 1) / per_group;
-    hipLaunchKernelGGL((aidw_f32_fused<K, Q, TRACK>), dim3((unsigned)groups), dim3(kGroupSize),
-                       0, stream, p);
+__global__ __launch_bounds__(kGroupSize) void aidw_f32_fused(ProblemF32 p) {
+    fused_tile<K, Q, TRACK>(p, wave_id() * Q * kWaveSize);
+}
+
+// ---- batched: waves claim (problem, tile) items ------------------------------
+template <int K>
+__global__ __launch_bounds__(kGroupSize) void aidw_f32_batch(const ProblemF32* __restrict__ probs,
+                                                             const BatchItem* __restrict__ items,
+                                                             int n_items, int* __restrict__ counter) {
+    for (;;) {
+        int it = 0;
+        if (lane_id() == 0) it = atomicAdd(counter, 1);
+        it = __builtin_amdgcn_readfirstlane(it);
+        if (it >= n_items) break;
+        const BatchItem w = items[it];
+        fused_tile<K, 1, false>(probs[w.problem], w.base);
+    }
+}
+
+__global__ void aidw_reset_counter(int* __restrict__ counter) {
+    if (threadIdx.x == 0) *counter = 0;
+}
+
+// ---- split-m ------------------------------------------------------------------
+// Waves are numbered segment-major so that the waves of one workgroup share a
+// data segment.  Partial lists: part[(seg * K + i) * n + q].
+template <int K>
+__global__ __launch_bounds__(kGroupSize) void aidw_f32_knn_part(ProblemF32 p, SplitPlan sp,
+                                                                float* __restrict__ part) {
+    const int wave = wave_id();
+    const int seg = wave / sp.tiles;
+    const int tile = wave - seg * sp.tiles;
+    if (seg >= sp.segments) return;
+    const int j0 = seg * sp.seg_len;
+    const int j1 = min(p.m, j0 + sp.seg_len);
+    int qi[1];
+    float qx[1], qy[1];
+    load_queries<1>(p, tile * kWaveSize, qi, qx, qy);
+    float top[1][K];
+    int tix[1][1];
+    init_lists<K, 1, false>(top, tix, p.ap.k);
+    scan_knn<K, 1, false>(as_const(p.dx), as_const(p.dy), j0, j1, qx, qy, top, tix);
+    if (qi[0] < p.n) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) part[((int64_t)seg * K + i) * p.n + qi[0]] = top[0][i];
+    }
+}
+
+// Merge the segment lists of each query (in segment order), then alpha.
+template <int K>
+__global__ __launch_bounds__(kGroupSize) void aidw_f32_knn_merge(ProblemF32 p, SplitPlan sp,
+                                                                 const float* __restrict__ part,
+                                                                 float* __restrict__ qpar) {
+    const int q = blockIdx.x * kGroupSize + threadIdx.x;
+    if (q >= p.n) return;
+    const int pad = K - p.ap.k;
+    float top[1][K];
+    int tix[1][1];
+    init_lists<K, 1, false>(top, tix, p.ap.k);
+    for (int seg = 0; seg < sp.segments; ++seg) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            if (i < pad) continue;
+            const float v = part[((int64_t)seg * K + i) * p.n + q];
+            if (v < top[0][K - 1]) list_insert<K>(top[0], v);
+        }
+    }
+    double r_obs, al;
+    float na, aL0;
+    query_power<K>(top[0], p.ap, r_obs, al, na, aL0);
+    qpar[q] = na;
+    qpar[p.n + q] = aL0;
+    if (p.r_obs) p.r_obs[q] = r_obs;
+    if (p.alpha) p.alpha[q] = al;
+}
+
+// Per-segment weighted sums: psum[(seg * 2 + {0: sum w, 1: sum w z}) * n + q].
+__global__ __launch_bounds__(kGroupSize) void aidw_f32_wsum_part(ProblemF32 p, SplitPlan sp,
+                                                                 const float* __restrict__ qpar,
+                                                                 double* __restrict__ psum) {
+    const int wave = wave_id();
+    const int seg = wave / sp.tiles;
+    const int tile = wave - seg * sp.tiles;
+    if (seg >= sp.segments) return;
+    const int j0 = seg * sp.seg_len;
+    const int j1 = min(p.m, j0 + sp.seg_len);
+    int qi[1];
+    float qx[1], qy[1];
+    load_queries<1>(p, tile * kWaveSize, qi, qx, qy);
+    const int c = qi[0] < p.n ? qi[0] : p.n - 1;
+    float na[1] = {qpar[c]}, aL0[1] = {qpar[p.n + c]};
+    double Sw[1] = {0.0}, Swz[1] = {0.0};
+    scan_wsum_any<1>(as_const(p.dx), as_const(p.dy), as_const(p.dz), j0, j1, qx, qy, na, aL0, Sw,
+                     Swz);
+    if (qi[0] < p.n) {
+        psum[((int64_t)seg * 2 + 0) * p.n + qi[0]] = Sw[0];
+        psum[((int64_t)seg * 2 + 1) * p.n + qi[0]] = Swz[0];
+    }
+}
+
+__global__ __launch_bounds__(kGroupSize) void aidw_f32_wsum_reduce(ProblemF32 p, SplitPlan sp,
+                                                                   const double* __restrict__ psum) {
+    const int q = blockIdx.x * kGroupSize + threadIdx.x;
+    if (q >= p.n) return;
+    double Sw = 0.0, Swz = 0.0;
+    for (int seg = 0; seg < sp.segments; ++seg) {
+        Sw += psum[((int64_t)seg * 2 + 0) * p.n + q];
+        Swz += psum[((int64_t)seg * 2 + 1) * p.n + q];
+    }
+    p.out[q] = (float)(Swz / Sw);
+}
+
+// ---- host-side launchers ----------------------------------------------------------
+size_t occupancy_lds(const LaunchF32& cfg) {
+    // Each workgroup holds one wave per SIMD, so W resident workgroups per CU
+    // mean W waves per SIMD; reserving kLdsPerCU / W bytes caps it at W.
+    if (cfg.max_waves_per_simd <= 0) return 0;
+    return (size_t)(kLdsPerCU / cfg.max_waves_per_simd) & ~(size_t)1023;
+}
+
+template <typename Kern>
+hipError_t allow_lds(Kern kern, size_t lds) {
+    if (lds <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+}
+
+unsigned groups_for(int64_t waves) {
+    return (unsigned)((waves + kWavesPerGroup - 1) / kWavesPerGroup);
+}
+
+template <int K, int Q, bool TRACK>
+hipError_t launch_fused(const ProblemF32& p, const LaunchF32& cfg, hipStream_t stream) {
+    const int64_t tiles = (p.n + (int64_t)kWaveSize * Q - 1) / ((int64_t)kWaveSize * Q);
+    const size_t lds = occupancy_lds(cfg);
+    hipError_t e = allow_lds(aidw_f32_fused<K, Q, TRACK>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((aidw_f32_fused<K, Q, TRACK>), dim3(groups_for(tiles)), dim3(kGroupSize),
+                       lds, stream, p);
     return hipGetLastError();
 }
 
 template <int K>
-hipError_t launch_k(const ProblemF32& p, const LaunchF32& cfg, hipStream_t stream) {
-    if (p.knn) return launch_kq<K, 1, true>(p, stream);
+hipError_t launch_split(const ProblemF32& p, const SplitPlan& sp, const SplitWorkspace& ws,
+                        hipStream_t stream) {
+    const unsigned g_part = groups_for((int64_t)sp.tiles * sp.segments);
+    const unsigned g_query = (unsigned)((p.n + kGroupSize - 1) / kGroupSize);
+    hipLaunchKernelGGL((aidw_f32_knn_part<K>), dim3(g_part), dim3(kGroupSize), 0, stream, p, sp,
+                       ws.part);
+    hipLaunchKernelGGL((aidw_f32_knn_merge<K>), dim3(g_query), dim3(kGroupSize), 0, stream, p, sp,
+                       ws.part, ws.qpar);
+    hipLaunchKernelGGL(aidw_f32_wsum_part, dim3(g_part), dim3(kGroupSize), 0, stream, p, sp,
+                       ws.qpar, ws.psum);
+    hipLaunchKernelGGL(aidw_f32_wsum_reduce, dim3(g_query), dim3(kGroupSize), 0, stream, p, sp,
+                       ws.psum);
+    return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_single_k(const ProblemF32& p, const LaunchF32& cfg, const SplitPlan* sp,
+                           const SplitWorkspace* ws, hipStream_t stream) {
+    if (p.knn) return launch_fused<K, 1, true>(p, cfg, stream);
+    if (sp && sp->segments > 1) return launch_split<K>(p, *sp, *ws, stream);
     switch (cfg.q_per_lane) {
-        case 1: return launch_kq<K, 1, false>(p, stream);
-        case 2: return launch_kq<K, 2, false>(p, stream);
-        case 4: return launch_kq<K, 4, false>(p, stream);
+        case 1: return launch_fused<K, 1, false>(p, cfg, stream);
+        case 2: return launch_fused<K, 2, false>(p, cfg, stream);
+        case 4: return launch_fused<K, 4, false>(p, cfg, stream);
         default: return hipErrorInvalidValue;
     }
 }
 
+template <int K>
+hipError_t launch_batch_k(const BatchLaunch& b, hipStream_t stream) {
+    hipLaunchKernelGGL(aidw_reset_counter, dim3(1), dim3(64), 0, stream, b.counter);
+    hipLaunchKernelGGL((aidw_f32_batch<K>), dim3(b.groups), dim3(kGroupSize), 0, stream,
+                       b.problems, b.items, b.n_items, b.counter);
+    return hipGetLastError();
+}
+
+template <int K>
+int batch_occupancy_k() {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, aidw_f32_batch<K>, kGroupSize, 0) !=
+        hipSuccess)
+        return 0;
+    return blocks;
+}
+
+#define AIDW_K_DISPATCH(K_RUNTIME, CALL) \
+    switch (K_RUNTIME) {                 \
+        case 4: return CALL(4);          \
+        case 8: return CALL(8);          \
+        case 10: return CALL(10);        \
+        case 12: return CALL(12);        \
+        case 16: return CALL(16);        \
+        case 20: return CALL(20);        \
+        case 24: return CALL(24);        \
+        case 32: return CALL(32);        \
+        default: break;                  \
+    }
+
 }  // namespace
 
-hipError_t launch_aidw_f32(const ProblemF32& p, const LaunchF32& cfg, hipStream_t stream) {
+hipError_t launch_aidw_f32(const ProblemF32& p, const LaunchF32& cfg, const SplitPlan* sp,
+                           const SplitWorkspace* ws, hipStream_t stream) {
     if (p.n <= 0) return hipSuccess;
-    switch (k_bucket(p.ap.k)) {
-        case 4: return launch_k<4>(p, cfg, stream);
-        case 8: return launch_k<8>(p, cfg, stream);
-        case 10: return launch_k<10>(p, cfg, stream);
-        case 12: return launch_k<12>(p, cfg, stream);
-        case 16: return launch_k<16>(p, cfg, stream);
-        case 20: return launch_k<20>(p, cfg, stream);
-        case 24: return launch_k<24>(p, cfg, stream);
-        case 32: return launch_k<32>(p, cfg, stream);
-        default: return hipErrorInvalidValue;
-    }
+#define CALL(KK) launch_single_k<KK>(p, cfg, sp, ws, stream)
+    AIDW_K_DISPATCH(k_bucket(p.ap.k), CALL)
+#undef CALL
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_aidw_f32_batch(const BatchLaunch& b, hipStream_t stream) {
+    if (b.n_items <= 0) return hipSuccess;
+#define CALL(KK) launch_batch_k<KK>(b, stream)
+    AIDW_K_DISPATCH(b.K, CALL)
+#undef CALL
+    return hipErrorInvalidValue;
+}
+
+int batch_blocks_per_cu(int K) {
+#define CALL(KK) batch_occupancy_k<KK>()
+    AIDW_K_DISPATCH(K, CALL)
+#undef CALL
+    return 0;
 }
 
 }  // namespace aidw

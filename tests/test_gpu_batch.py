@@ -1,0 +1,229 @@
+"""Batched launches (many independent problems, one persistent launch, graph
+replay) and the split-m path for problems with few queries.  All results are
+checked against the FP64 oracle, and batched results against the same
+problems run alone."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1511_02186_amd import aidw, workloads
+
+pytestmark = pytest.mark.gpu
+TOL_F32 = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    c = aidw.Context(0)
+    yield c
+    c.close()
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def rel_err(got, want, scale):
+    diff = np.abs(np.asarray(got, dtype=np.float64) - want)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(scale > 0, diff / scale, np.where(diff == 0, 0.0, np.inf))
+
+
+def ref(inst, idx):
+    a = (inst.data_x, inst.data_y)
+    kw = dict(alpha_levels=inst.levels, R_min=inst.R_min, R_max=inst.R_max, area=inst.area)
+    out = oracle.run(*a, inst.data_z, inst.query_x[idx], inst.query_y[idx], inst.k, **kw)
+    scale = oracle.run(*a, np.abs(inst.data_z), inst.query_x[idx], inst.query_y[idx], inst.k,
+                       **kw)
+    return out, scale
+
+
+class Dev:
+    """Device copies of one instance plus its output buffer."""
+
+    def __init__(self, torch, inst):
+        self.inst = inst
+        self.data_xy, self.data_z, self.query_xy = aidw.to_device(inst)
+        self.out = torch.full((inst.n,), float("nan"), device="cuda")
+
+    def problem(self, ctx):
+        i = self.inst
+        return ctx.problem(self.data_xy, self.data_z, self.query_xy, i.k, self.out, i.levels,
+                           i.R_min, i.R_max, i.area)
+
+
+def mixed_instances(count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        m = int(rng.integers(1, 9000))
+        n = int(rng.integers(0, 700))
+        k = int(rng.choice([1, 8, 10, 15, 32]))
+        k = min(k, m)
+        if rng.uniform() < 0.5:
+            inst = workloads.uniform_unit(m, n, 1000 + i, k)
+        else:
+            inst = workloads.clustered(m, n, 1000 + i, k, on_point=0.05)
+        if inst.area <= 0:
+            inst.area = 1.0
+        out.append(inst)
+    return out
+
+
+def run_alone(ctx, torch, dev):
+    ctx.set_tuning(q_per_lane=1, split_segments=1)
+    try:
+        i = dev.inst
+        r = ctx.interpolate(dev.data_xy, dev.data_z, dev.query_xy, i.k, i.levels, i.R_min,
+                            i.R_max, i.area)
+    finally:
+        ctx.set_tuning()
+    torch.cuda.synchronize()
+    return r.cpu().numpy()
+
+
+def test_batch_is_bitwise_equal_to_problems_alone(ctx, torch):
+    insts = mixed_instances(24, 1)
+    devs = [Dev(torch, i) for i in insts]
+    ctx.bind_current_stream()
+    aidw.check(aidw.aidw_interpolate_batch(ctx.h, [d.problem(ctx) for d in devs]))
+    torch.cuda.synchronize()
+    for d in devs:
+        got = d.out.cpu().numpy()
+        alone = run_alone(ctx, torch, d)
+        assert np.array_equal(got, alone), d.inst.name
+        if d.inst.n:
+            idx = np.unique(np.linspace(0, d.inst.n - 1, 9).astype(int))
+            o, scale = ref(d.inst, idx)
+            assert rel_err(got[idx], o, scale).max() <= TOL_F32, d.inst.name
+
+
+def test_graph_replays_follow_input_changes(ctx, torch):
+    insts = mixed_instances(10, 2)
+    devs = [Dev(torch, i) for i in insts]
+    ctx.bind_current_stream()
+    b = aidw.aidw_batch_create(ctx.h, [d.problem(ctx) for d in devs])
+    try:
+        rng = np.random.default_rng(0)
+        for replay in range(3):
+            # eager work between replays: new query positions in place
+            for d in devs:
+                if d.inst.n:
+                    d.inst.query_x[:] = rng.uniform(0, 1, d.inst.n).astype(np.float32)
+                    d.inst.query_y[:] = rng.uniform(0, 1, d.inst.n).astype(np.float32)
+                    d.query_xy.copy_(torch.from_numpy(d.inst.query_xy()))
+                d.out.fill_(float("nan"))
+            torch.cuda.synchronize()
+            aidw.check(aidw.aidw_batch_launch(b))
+            for d in devs:
+                got = d.out.cpu().numpy()
+                assert np.array_equal(got, run_alone(ctx, torch, d)), (replay, d.inst.name)
+    finally:
+        aidw.aidw_batch_destroy(b)
+
+
+def test_batch_argument_errors(ctx, torch):
+    inst = workloads.uniform_unit(500, 100, 3, 8)
+    d = Dev(torch, inst)
+    good = d.problem(ctx)
+    bad = d.problem(ctx)
+    bad.k = 0
+    st = aidw.aidw_interpolate_batch(ctx.h, [good, good, bad])
+    assert st == aidw.AIDW_EINVAL and "problem 2" in aidw.last_error()
+    knn = torch.empty((inst.n, inst.k), dtype=torch.int32, device="cuda")
+    with_knn = d.problem(ctx)
+    with_knn.knn_idx = knn.data_ptr()
+    assert aidw.aidw_interpolate_batch(ctx.h, [with_knn]) == aidw.AIDW_EINVAL
+    inst64 = workloads.uniform_unit(500, 100, 3, 8, dtype=np.float64)
+    d64 = Dev(torch, inst64)
+    d64.out = torch.empty(inst64.n, dtype=torch.float64, device="cuda")
+    assert aidw.aidw_interpolate_batch(ctx.h, [d64.problem(ctx)]) == aidw.AIDW_EINVAL
+    assert aidw.aidw_interpolate_batch(ctx.h, []) == aidw.AIDW_OK
+
+
+def test_batched_config_512_instances(ctx, torch):
+    insts = workloads.batched()  # 512 problems, m in [1024, 65536], n in [1024, 32768]
+    pairs = sum(i.pair_evals() for i in insts)
+    say("batched: %d problems, %.3e pair evaluations" % (len(insts), pairs))
+    devs = [Dev(torch, i) for i in insts]
+    ctx.bind_current_stream()
+    b = aidw.aidw_batch_create(ctx.h, [d.problem(ctx) for d in devs])
+    try:
+        aidw.check(aidw.aidw_batch_launch(b))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        aidw.check(aidw.aidw_batch_launch(b, aidw.AIDW_FLAG_ASYNC))
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        say("batched: %.2f ms, %.3e pair-evals/s" % (ms, pairs / (ms * 1e-3)))
+    finally:
+        aidw.aidw_batch_destroy(b)
+    rng = np.random.default_rng(5)
+    worst = 0.0
+    for d in devs:
+        got = d.out.cpu().numpy()
+        idx = np.sort(rng.choice(d.inst.n, 3, replace=False))
+        o, scale = ref(d.inst, idx)
+        worst = max(worst, rel_err(got[idx], o, scale).max())
+    say("batched: max err %.3e over %d sampled queries" % (worst, 3 * len(devs)))
+    assert worst <= TOL_F32
+    for d in devs[::64]:
+        assert np.array_equal(d.out.cpu().numpy(), run_alone(ctx, torch, d)), d.inst.name
+
+
+# ---- split-m ---------------------------------------------------------------
+
+def _run(ctx, torch, inst, segments=0, diag=False):
+    data_xy, data_z, query_xy = aidw.to_device(inst)
+    ctx.set_tuning(split_segments=segments)
+    try:
+        r = ctx.interpolate(data_xy, data_z, query_xy, inst.k, inst.levels, inst.R_min,
+                            inst.R_max, inst.area, diag=diag)
+    finally:
+        ctx.set_tuning()
+    torch.cuda.synchronize()
+    return tuple(t.cpu().numpy() for t in r) if diag else r.cpu().numpy()
+
+
+@pytest.mark.parametrize("segments", [2, 7, 64, 1000])
+@pytest.mark.parametrize("k", [1, 10, 15, 32])
+def test_split_matches_unsplit_and_oracle(ctx, torch, segments, k):
+    inst = workloads.clustered(m=50003, n=700, seed=segments + k, k=k, on_point=0.03)
+    whole, r0, a0, _ = _run(ctx, torch, inst, segments=1, diag=True)
+    split, r1, a1, _ = _run(ctx, torch, inst, segments=segments, diag=True)
+    assert np.array_equal(r0, r1)  # same k nearest distances, same order of summation
+    assert np.array_equal(a0, a1)
+    assert np.allclose(split, whole, rtol=2e-7, atol=0)
+    idx = np.arange(0, inst.n, 11)
+    o, scale = ref(inst, idx)
+    assert rel_err(split[idx], o, scale).max() <= TOL_F32
+
+
+@pytest.mark.parametrize("m,n", [(4096, 1), (300000, 64), (1 << 20, 256), (65536, 5000)])
+def test_automatic_split_for_few_queries(ctx, torch, m, n):
+    inst = workloads.paper_scale(m=m, n=n, seed=m % 97 + n, k=15)
+    out = _run(ctx, torch, inst)
+    idx = np.unique(np.linspace(0, n - 1, min(n, 24)).astype(int))
+    o, scale = ref(inst, idx)
+    assert rel_err(out[idx], o, scale).max() <= TOL_F32
+
+
+def test_split_with_alpha_zero_and_coincident_queries(ctx, torch):
+    inst = workloads.uniform_unit(40000, 300, 7, 10)
+    inst.query_x[:30] = inst.data_x[:30]
+    inst.query_y[:30] = inst.data_y[:30]
+    for levels in [(1, 2, 3, 4, 5), (0, 0, 0, 0, 0)]:
+        inst.levels = levels
+        out = _run(ctx, torch, inst, segments=16)
+        o, scale = ref(inst, np.arange(inst.n))
+        assert rel_err(out, o, scale).max() <= TOL_F32
+        if levels[0] > 0:
+            assert np.array_equal(out[:30], inst.data_z[:30])
