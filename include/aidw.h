@@ -175,6 +175,88 @@ void aidw_batch_destroy(aidw_batch_t b);
 aidw_status aidw_interpolate_batch(aidw_t h, const aidw_problem* problems, int count,
                                    unsigned flags);
 
+/* ---- Serving: continuous batching of submitted jobs -----------------------
+ * A server owns a worker thread, `streams` HIP streams and a device arena.
+ * Submitted jobs are admitted first-in first-out while the arena has room
+ * for their workspace (jobs whose data set exceeds `segment_points` points
+ * are split into data segments and need a workspace; the others need none).
+ * Each scheduling tick packs work items of all admitted jobs -- jobs that
+ * waited longer than max_wait_s first, then the shortest remaining work --
+ * into one launch of about tick_pair_evals distance evaluations, and up to
+ * `streams` ticks run at once, so jobs that arrive while others are on the
+ * GPU start with the next tick.  A job's result does not depend on which
+ * other jobs it shares ticks with.  All jobs are FP32-scaled. */
+
+/* A data set copied into library-owned device memory (counted against the
+ * handle's budget).  data_xy [2][m] and data_z [m] are float device
+ * pointers; the copy is complete when the call returns. */
+aidw_status aidw_dataset_register(aidw_t h, const void* data_xy, const void* data_z, int64_t m,
+                                  double area, uint64_t* id);
+/* Free a registered data set.  AIDW_EAGAIN while unfinished jobs read it,
+ * AIDW_ENOTFOUND for an unknown id. */
+aidw_status aidw_dataset_release(aidw_t h, uint64_t id);
+
+typedef struct aidw_server_options {
+    size_t arena_bytes;       /* device workspace for admitted split jobs, counted
+                                 against the handle's budget (0: 2 GiB) */
+    int streams;              /* ticks in flight, 1..8 (0: 2) */
+    double tick_pair_evals;   /* distance evaluations per tick (0: 4e10) */
+    double max_wait_s;        /* jobs older than this are served first (0: 0.25) */
+    int64_t segment_points;   /* data points per segment of a split job (0: 32768) */
+} aidw_server_options;
+
+typedef struct aidw_server* aidw_server_t;
+
+/* Start a server on the handle's device (opt may be NULL).  The handle must
+ * outlive the server. */
+aidw_status aidw_server_create(aidw_t h, const aidw_server_options* opt, aidw_server_t* out);
+/* Finish every submitted job, then stop the worker and free the server. */
+void aidw_server_destroy(aidw_server_t s);
+
+/* One job.  Pointers are float device pointers that must stay valid (and
+ * the inputs unchanged) until the job is reported done. */
+typedef struct aidw_job {
+    uint64_t dataset;        /* a registered data set, or 0 to use the next four fields */
+    const void* data_xy;     /* [2][m] */
+    const void* data_z;      /* [m] */
+    int64_t m;
+    double area;             /* A of Eq. 2 */
+    const void* query_xy;    /* [2][n] */
+    int64_t n;
+    int k;
+    double alpha_levels[5];
+    double R_min, R_max;
+    void* out;               /* [n] float */
+    double* r_obs;           /* optional [n] */
+    double* alpha;           /* optional [n] */
+} aidw_job;
+
+/* Validate and enqueue a job; *ticket identifies it.  Thread-safe.  A job
+ * whose workspace can never fit the arena is accepted and reported as
+ * failed with AIDW_ENOMEM by aidw_poll. */
+aidw_status aidw_submit(aidw_server_t s, const aidw_job* job, uint64_t* ticket);
+/* AIDW_EAGAIN while the job is queued or running.  Once it has finished,
+ * returns AIDW_OK with *job_status (AIDW_OK or the job's error) and
+ * *latency_s (seconds from submission to completion), then forgets the
+ * ticket (later polls: AIDW_ENOTFOUND).  Thread-safe. */
+aidw_status aidw_poll(aidw_server_t s, uint64_t ticket, aidw_status* job_status,
+                      double* latency_s);
+/* aidw_poll until the job finishes or timeout_s passes (AIDW_EAGAIN);
+ * timeout_s < 0 waits indefinitely. */
+aidw_status aidw_wait(aidw_server_t s, uint64_t ticket, double timeout_s, aidw_status* job_status,
+                      double* latency_s);
+
+typedef struct aidw_server_counters {
+    uint64_t submitted, completed, failed, ticks;
+    double pair_evals;       /* distance evaluations of completed ticks */
+    size_t arena_in_use;
+    uint64_t queued, admitted;
+} aidw_server_counters;
+
+/* Counters of the server.  Returns the first device error the worker met,
+ * if any. */
+aidw_status aidw_server_stats(aidw_server_t s, aidw_server_counters* out);
+
 /* Wait until all work issued on the handle's stream has finished. */
 aidw_status aidw_synchronize(aidw_t h);
 

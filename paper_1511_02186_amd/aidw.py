@@ -59,6 +59,38 @@ class aidw_tuning(ctypes.Structure):
                 ("split_segments", ctypes.c_int)]
 
 
+class aidw_server_options(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_size_t), ("streams", ctypes.c_int),
+                ("tick_pair_evals", ctypes.c_double), ("max_wait_s", ctypes.c_double),
+                ("segment_points", ctypes.c_int64)]
+
+
+class aidw_job(ctypes.Structure):
+    _fields_ = [
+        ("dataset", ctypes.c_uint64),
+        ("data_xy", ctypes.c_void_p),
+        ("data_z", ctypes.c_void_p),
+        ("m", ctypes.c_int64),
+        ("area", ctypes.c_double),
+        ("query_xy", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("k", ctypes.c_int),
+        ("alpha_levels", ctypes.c_double * 5),
+        ("R_min", ctypes.c_double),
+        ("R_max", ctypes.c_double),
+        ("out", ctypes.c_void_p),
+        ("r_obs", ctypes.c_void_p),
+        ("alpha", ctypes.c_void_p),
+    ]
+
+
+class aidw_server_counters(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("ticks", ctypes.c_uint64),
+                ("pair_evals", ctypes.c_double), ("arena_in_use", ctypes.c_size_t),
+                ("queued", ctypes.c_uint64), ("admitted", ctypes.c_uint64)]
+
+
 class AidwError(RuntimeError):
     def __init__(self, status, message):
         super().__init__("%s: %s" % (status_name(status), message))
@@ -85,6 +117,20 @@ _SIGNATURES = {
     "aidw_batch_destroy": (None, [ctypes.c_void_p]),
     "aidw_interpolate_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem),
                                               ctypes.c_int, ctypes.c_uint]),
+    "aidw_dataset_register": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int64, ctypes.c_double,
+                                             ctypes.POINTER(ctypes.c_uint64)]),
+    "aidw_dataset_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "aidw_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_server_options),
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "aidw_server_destroy": (None, [ctypes.c_void_p]),
+    "aidw_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_job),
+                                   ctypes.POINTER(ctypes.c_uint64)]),
+    "aidw_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
+                                 ctypes.POINTER(ctypes.c_double)]),
+    "aidw_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double,
+                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
+    "aidw_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_server_counters)]),
     "aidw_last_error": (ctypes.c_char_p, []),
     "aidw_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "aidw_version": (ctypes.c_int, []),
@@ -190,6 +236,55 @@ def aidw_version() -> int:
     return lib().aidw_version()
 
 
+def aidw_dataset_register(h, data_xy_ptr, data_z_ptr, m, area) -> int:
+    i = ctypes.c_uint64()
+    check(lib().aidw_dataset_register(h, data_xy_ptr, data_z_ptr, int(m), float(area),
+                                      ctypes.byref(i)))
+    return i.value
+
+
+def aidw_dataset_release(h, dataset_id) -> int:
+    return lib().aidw_dataset_release(h, int(dataset_id))
+
+
+def aidw_server_create(h, arena_bytes=0, streams=0, tick_pair_evals=0.0, max_wait_s=0.0,
+                       segment_points=0) -> int:
+    opt = aidw_server_options(int(arena_bytes), int(streams), float(tick_pair_evals),
+                              float(max_wait_s), int(segment_points))
+    s = ctypes.c_void_p()
+    check(lib().aidw_server_create(h, ctypes.byref(opt), ctypes.byref(s)))
+    return s.value
+
+
+def aidw_server_destroy(s) -> None:
+    lib().aidw_server_destroy(s)
+
+
+def aidw_submit(s, job: aidw_job) -> int:
+    t = ctypes.c_uint64()
+    check(lib().aidw_submit(s, ctypes.byref(job), ctypes.byref(t)))
+    return t.value
+
+
+def aidw_poll(s, ticket):
+    """(status, job_status, latency_s); status AIDW_EAGAIN while pending."""
+    js, lat = ctypes.c_int(), ctypes.c_double()
+    st = lib().aidw_poll(s, int(ticket), ctypes.byref(js), ctypes.byref(lat))
+    return st, js.value, lat.value
+
+
+def aidw_wait(s, ticket, timeout_s=-1.0):
+    js, lat = ctypes.c_int(), ctypes.c_double()
+    st = lib().aidw_wait(s, int(ticket), float(timeout_s), ctypes.byref(js), ctypes.byref(lat))
+    return st, js.value, lat.value
+
+
+def aidw_server_stats(s):
+    c = aidw_server_counters()
+    st = lib().aidw_server_stats(s, ctypes.byref(c))
+    return st, {f: getattr(c, f) for f, _ in c._fields_}
+
+
 # ---- torch convenience layer ------------------------------------------------
 
 class Context:
@@ -287,6 +382,30 @@ class Context:
         if diag:
             return out, r_obs, alpha, knn
         return out
+
+
+def make_job(query_xy, k, out, alpha_levels=(1, 2, 3, 4, 5), R_min=0.0, R_max=2.0,
+             dataset=0, data_xy=None, data_z=None, area=None, r_obs=None, alpha=None):
+    """aidw_job over torch tensors (float32, on the GPU): a registered dataset
+    id, or data_xy/data_z/area."""
+    j = aidw_job()
+    j.dataset = int(dataset)
+    if not dataset:
+        if data_xy is None or data_z is None or area is None:
+            raise ValueError("give a dataset id or data_xy, data_z and area")
+        j.data_xy = data_xy.data_ptr()
+        j.data_z = data_z.data_ptr()
+        j.m = data_z.numel()
+        j.area = float(area)
+    j.query_xy = query_xy.data_ptr()
+    j.n = out.numel()
+    j.k = int(k)
+    j.alpha_levels = (ctypes.c_double * 5)(*[float(a) for a in alpha_levels])
+    j.R_min, j.R_max = float(R_min), float(R_max)
+    j.out = out.data_ptr()
+    j.r_obs = r_obs.data_ptr() if r_obs is not None else None
+    j.alpha = alpha.data_ptr() if alpha is not None else None
+    return j
 
 
 def to_device(inst, device="cuda"):

@@ -12,12 +12,15 @@
 
 #include "../../include/aidw.h"
 #include "common.h"
+#include "handle.h"
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-aidw_status fail(aidw_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+namespace aidw {
+namespace detail {
+
 aidw_status fail(aidw_status s, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -32,19 +35,10 @@ aidw_status hip_fail(hipError_t e, const char* what) {
     return fail(AIDW_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-}  // namespace
+}  // namespace detail
+}  // namespace aidw
 
-struct aidw_ctx {
-    int device = 0;
-    aidw_precision default_precision = AIDW_FP32_SCALED;
-    size_t hbm_budget = 0;       // 0: unlimited
-    size_t hbm_in_use = 0;       // library-owned device bytes
-    hipStream_t stream = nullptr;
-    int cu_count = 0;
-    aidw_tuning tuning{0, 0, 0};  // zero fields: automatic
-    void* workspace = nullptr;    // split-m scratch, grown on demand
-    size_t workspace_bytes = 0;
-};
+using namespace aidw::detail;
 
 struct aidw_batch {
     aidw_t h = nullptr;
@@ -68,9 +62,10 @@ int k_bucket(int k) {
 
 }  // namespace aidw
 
-namespace {
+namespace aidw {
+namespace detail {
 
-bool finite(double v) { return std::isfinite(v); }
+static bool finite(double v) { return std::isfinite(v); }
 
 // Host-side validation of everything the kernels assume (include/aidw.h).
 aidw_status validate(const aidw_problem* p) {
@@ -109,6 +104,11 @@ aidw::AlphaParams alpha_params(const aidw_problem* p) {
     return ap;
 }
 
+}  // namespace detail
+}  // namespace aidw
+
+namespace {
+
 int default_q_per_lane(const aidw_ctx*, int64_t) {
     // One query per lane: the lean register footprint (about 60 VGPRs) keeps
     // 8 waves per SIMD resident, which hides the scalar-load and
@@ -118,6 +118,11 @@ int default_q_per_lane(const aidw_ctx*, int64_t) {
 }
 
 // Library-owned device allocations are counted against the handle's budget.
+}  // namespace
+
+namespace aidw {
+namespace detail {
+
 aidw_status device_alloc(aidw_t h, size_t bytes, void** out) {
     *out = nullptr;
     if (bytes == 0) return AIDW_OK;
@@ -129,6 +134,7 @@ aidw_status device_alloc(aidw_t h, size_t bytes, void** out) {
         *out = nullptr;
         return fail(AIDW_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
     }
+    std::lock_guard<std::mutex> lk(h->mu);
     h->hbm_in_use += bytes;
     return AIDW_OK;
 }
@@ -136,8 +142,14 @@ aidw_status device_alloc(aidw_t h, size_t bytes, void** out) {
 void device_free(aidw_t h, void* p, size_t bytes) {
     if (!p) return;
     (void)hipFree(p);
+    std::lock_guard<std::mutex> lk(h->mu);
     h->hbm_in_use -= bytes;
 }
+
+}  // namespace detail
+}  // namespace aidw
+
+namespace {
 
 aidw_status ensure_workspace(aidw_t h, size_t bytes) {
     if (bytes <= h->workspace_bytes) return AIDW_OK;
@@ -173,9 +185,14 @@ aidw::SplitPlan split_plan(const aidw_ctx* h, int64_t m, int64_t n) {
     return sp;
 }
 
-size_t split_workspace_bytes(const aidw::SplitPlan& sp, int K, int64_t n, aidw::SplitWorkspace* ws,
+}  // namespace
+
+namespace aidw {
+namespace detail {
+
+size_t split_workspace_bytes(const aidw::SplitPlan& sp, int k, int64_t n, aidw::SplitWorkspace* ws,
                              char* base) {
-    const size_t part = (size_t)sp.segments * K * n * sizeof(float);
+    const size_t part = (size_t)sp.segments * k * n * sizeof(float);
     const size_t qpar = 2 * (size_t)n * sizeof(float);
     const size_t psum = (size_t)sp.segments * 2 * n * sizeof(double);
     const size_t a = 256;
@@ -198,6 +215,11 @@ aidw::ProblemF32 problem_f32(const aidw_problem* p) {
                             alpha_params(p)};
 }
 
+}  // namespace detail
+}  // namespace aidw
+
+namespace {
+
 aidw_status run_problem(aidw_t h, const aidw_problem* p) {
     aidw_status st = validate(p);
     if (st != AIDW_OK) return st;
@@ -213,10 +235,9 @@ aidw_status run_problem(aidw_t h, const aidw_problem* p) {
         aidw::SplitWorkspace ws{};
         if (!p->knn_idx) sp = split_plan(h, m, n);
         if (sp.segments > 1) {
-            const int K = aidw::k_bucket(p->k);
-            aidw_status st = ensure_workspace(h, split_workspace_bytes(sp, K, n, nullptr, nullptr));
+            aidw_status st = ensure_workspace(h, split_workspace_bytes(sp, p->k, n, nullptr, nullptr));
             if (st != AIDW_OK) return st;
-            split_workspace_bytes(sp, K, n, &ws, static_cast<char*>(h->workspace));
+            split_workspace_bytes(sp, p->k, n, &ws, static_cast<char*>(h->workspace));
         }
         e = aidw::launch_aidw_f32(q, cfg, &sp, &ws, h->stream);
     } else {

@@ -78,7 +78,7 @@ struct SplitPlan {
 
 // Device workspace of a split launch (sizes in split_workspace_bytes).
 struct SplitWorkspace {
-    float* part;   // [segments][K][n] per-segment k-nearest lists
+    float* part;   // [segments][k][n] per-segment k nearest squared distances
     float* qpar;   // [2][n] pass-2 exponent terms per query
     double* psum;  // [segments][2][n] per-segment sum w and sum w z
 };
@@ -99,6 +99,39 @@ struct BatchLaunch {
     int groups;
     int K;                       // register bucket >= every problem's k
 };
+
+// ---- serving: one launch per scheduling tick --------------------------------
+// A job in a tick: its problem, its split and, for split jobs, its device
+// workspace (partial lists, exponent terms, partial sums and two per-tile
+// arrival counters that the last segment of a tile uses to merge or reduce).
+struct ServeJob {
+    ProblemF32 p;
+    SplitPlan sp;       // sp.segments == 1: fused items only
+    SplitWorkspace ws;  // unused when sp.segments == 1
+    int* knn_arrivals;  // [tiles], zero before the job's first pass-1 item
+    int* sum_arrivals;  // [tiles], zero before the job's first pass-2 item
+};
+
+enum ServePhase : int { kServeFused = 0, kServeKnn = 1, kServeSum = 2 };
+
+struct ServeItem {
+    int job;    // index into the tick's ServeJob array
+    int phase;  // ServePhase
+    int tile;   // 64-query tile
+    int seg;    // data segment (split phases)
+};
+
+struct ServeLaunch {
+    const ServeJob* jobs;    // device array
+    const ServeItem* items;  // device array
+    int* counter;            // device int, reset by the launch
+    int n_items;
+    int groups;
+    int K;
+};
+
+hipError_t launch_aidw_f32_serve(const ServeLaunch& s, hipStream_t stream);
+int serve_blocks_per_cu(int K);
 
 hipError_t launch_aidw_f32(const ProblemF32& p, const LaunchF32& cfg, const SplitPlan* sp,
                            const SplitWorkspace* ws, hipStream_t stream);

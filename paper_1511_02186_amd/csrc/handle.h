@@ -1,0 +1,55 @@
+// Internal definition of the library handle and the host helpers shared by
+// the translation units that implement the C ABI (api.hip, serve.hip).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <mutex>
+#include <unordered_map>
+
+#include "../../include/aidw.h"
+#include "common.h"
+
+// A data set copied into library-owned device memory (aidw_dataset_register).
+struct aidw_dataset_rec {
+    float* xy = nullptr;  // [2][m]
+    float* z = nullptr;   // [m]
+    int64_t m = 0;
+    double area = 0.0;
+    size_t bytes = 0;
+    int refs = 0;         // jobs in flight that read it
+};
+
+struct aidw_ctx {
+    int device = 0;
+    aidw_precision default_precision = AIDW_FP32_SCALED;
+    size_t hbm_budget = 0;        // 0: unlimited
+    size_t hbm_in_use = 0;        // library-owned device bytes
+    hipStream_t stream = nullptr;
+    int cu_count = 0;
+    aidw_tuning tuning{0, 0, 0};  // zero fields: automatic
+    void* workspace = nullptr;    // split-m scratch, grown on demand
+    size_t workspace_bytes = 0;
+    // Registered data sets; the mutex also guards hbm_in_use, which servers
+    // running on their own threads update.
+    std::mutex mu;
+    std::unordered_map<uint64_t, aidw_dataset_rec> datasets;
+    uint64_t next_dataset = 1;
+};
+
+namespace aidw {
+namespace detail {
+
+aidw_status fail(aidw_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+aidw_status hip_fail(hipError_t e, const char* what);
+aidw_status validate(const aidw_problem* p);
+AlphaParams alpha_params(const aidw_problem* p);
+ProblemF32 problem_f32(const aidw_problem* p);
+aidw_status device_alloc(aidw_t h, size_t bytes, void** out);
+void device_free(aidw_t h, void* p, size_t bytes);
+// Bytes of a split workspace; with ws/base given, also lays it out at base.
+size_t split_workspace_bytes(const SplitPlan& sp, int k, int64_t n, SplitWorkspace* ws,
+                             char* base);
+
+}  // namespace detail
+}  // namespace aidw

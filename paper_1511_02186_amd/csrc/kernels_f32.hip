@@ -306,9 +306,47 @@ __global__ void aidw_reset_counter(int* __restrict__ counter) {
     if (threadIdx.x == 0) *counter = 0;
 }
 
+// Per-segment k-nearest lists keep only the k real entries of each list,
+// laid out [segment][k][n], so the layout depends on the problem's k alone
+// and not on the register bucket of the kernel that writes or reads it.
+template <int K>
+__device__ __forceinline__ void store_partial(const float (&top)[K], const ProblemF32& p, int seg,
+                                              int q, float* __restrict__ part) {
+    if (q >= p.n) return;
+    const int k = p.ap.k, pad = K - k;
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        if (i >= pad) part[((int64_t)seg * k + (i - pad)) * p.n + q] = top[i];
+}
+
+// Fold the segment lists of query q in segment order (so equal distances
+// keep scan order), then alpha and the pass-2 exponent terms.
+template <int K>
+__device__ __forceinline__ void merge_tile(const ProblemF32& p, const SplitPlan& sp,
+                                           const float* __restrict__ part, float* __restrict__ qpar,
+                                           int q) {
+    const int k = p.ap.k;
+    float top[1][K];
+    int tix[1][1];
+    init_lists<K, 1, false>(top, tix, k);
+    for (int seg = 0; seg < sp.segments; ++seg) {
+        for (int i = 0; i < k; ++i) {
+            const float v = part[((int64_t)seg * k + i) * p.n + q];
+            if (v < top[0][K - 1]) list_insert<K>(top[0], v);
+        }
+    }
+    double r_obs, al;
+    float na, aL0;
+    query_power<K>(top[0], p.ap, r_obs, al, na, aL0);
+    qpar[q] = na;
+    qpar[p.n + q] = aL0;
+    if (p.r_obs) p.r_obs[q] = r_obs;
+    if (p.alpha) p.alpha[q] = al;
+}
+
 // ---- split-m ------------------------------------------------------------------
 // Waves are numbered segment-major so that the waves of one workgroup share a
-// data segment.  Partial lists: part[(seg * K + i) * n + q].
+// data segment.
 template <int K>
 __global__ __launch_bounds__(kGroupSize) void aidw_f32_knn_part(ProblemF32 p, SplitPlan sp,
                                                                 float* __restrict__ part) {
@@ -325,10 +363,7 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_knn_part(ProblemF32 p, Sp
     int tix[1][1];
     init_lists<K, 1, false>(top, tix, p.ap.k);
     scan_knn<K, 1, false>(as_const(p.dx), as_const(p.dy), j0, j1, qx, qy, top, tix);
-    if (qi[0] < p.n) {
-#pragma unroll
-        for (int i = 0; i < K; ++i) part[((int64_t)seg * K + i) * p.n + qi[0]] = top[0][i];
-    }
+    store_partial<K>(top[0], p, seg, qi[0], part);
 }
 
 // Merge the segment lists of each query (in segment order), then alpha.
@@ -338,25 +373,7 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_knn_merge(ProblemF32 p, S
                                                                  float* __restrict__ qpar) {
     const int q = blockIdx.x * kGroupSize + threadIdx.x;
     if (q >= p.n) return;
-    const int pad = K - p.ap.k;
-    float top[1][K];
-    int tix[1][1];
-    init_lists<K, 1, false>(top, tix, p.ap.k);
-    for (int seg = 0; seg < sp.segments; ++seg) {
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-            if (i < pad) continue;
-            const float v = part[((int64_t)seg * K + i) * p.n + q];
-            if (v < top[0][K - 1]) list_insert<K>(top[0], v);
-        }
-    }
-    double r_obs, al;
-    float na, aL0;
-    query_power<K>(top[0], p.ap, r_obs, al, na, aL0);
-    qpar[q] = na;
-    qpar[p.n + q] = aL0;
-    if (p.r_obs) p.r_obs[q] = r_obs;
-    if (p.alpha) p.alpha[q] = al;
+    merge_tile<K>(p, sp, part, qpar, q);
 }
 
 // Per-segment weighted sums: psum[(seg * 2 + {0: sum w, 1: sum w z}) * n + q].
@@ -393,6 +410,80 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_wsum_reduce(ProblemF32 p,
         Swz += psum[((int64_t)seg * 2 + 1) * p.n + q];
     }
     p.out[q] = (float)(Swz / Sw);
+}
+
+
+// ---- serving: fused tiles and split segments in one launch -----------------
+// Pass-1 segment items write their partial lists; the last segment of a tile
+// to arrive (an atomic count per tile, after a device-scope release fence)
+// merges the tile's lists in segment order and writes the exponent terms.
+// Pass-2 segment items run in a later launch; the last to arrive adds the
+// tile's segment sums in order and writes the outputs.  The arithmetic is
+// that of the split kernels above, so results do not depend on the order in
+// which items run.
+__device__ __forceinline__ bool last_arrival(int* counter, int expected) {
+    __threadfence();  // publish this item's partial results device-wide
+    int old = 0;
+    if (lane_id() == 0) old = atomicAdd(counter, 1);
+    old = __builtin_amdgcn_readfirstlane(old);
+    const bool last = old == expected - 1;
+    if (last) __threadfence();  // and see every other segment's
+    return last;
+}
+
+template <int K>
+__device__ __forceinline__ void serve_item(const ServeJob& J, const ServeItem& it) {
+    const ProblemF32& p = J.p;
+    if (it.phase == kServeFused) {
+        fused_tile<K, 1, false>(p, it.tile * kWaveSize);
+        return;
+    }
+    const int j0 = it.seg * J.sp.seg_len;
+    const int j1 = min(p.m, j0 + J.sp.seg_len);
+    int qi[1];
+    float qx[1], qy[1];
+    load_queries<1>(p, it.tile * kWaveSize, qi, qx, qy);
+    if (it.phase == kServeKnn) {
+        float top[1][K];
+        int tix[1][1];
+        init_lists<K, 1, false>(top, tix, p.ap.k);
+        scan_knn<K, 1, false>(as_const(p.dx), as_const(p.dy), j0, j1, qx, qy, top, tix);
+        store_partial<K>(top[0], p, it.seg, qi[0], J.ws.part);
+        if (last_arrival(&J.knn_arrivals[it.tile], J.sp.segments) && qi[0] < p.n)
+            merge_tile<K>(p, J.sp, J.ws.part, J.ws.qpar, qi[0]);
+        return;
+    }
+    const int c = qi[0] < p.n ? qi[0] : p.n - 1;
+    float na[1] = {J.ws.qpar[c]}, aL0[1] = {J.ws.qpar[p.n + c]};
+    double Sw[1] = {0.0}, Swz[1] = {0.0};
+    scan_wsum_any<1>(as_const(p.dx), as_const(p.dy), as_const(p.dz), j0, j1, qx, qy, na, aL0, Sw,
+                     Swz);
+    if (qi[0] < p.n) {
+        J.ws.psum[((int64_t)it.seg * 2 + 0) * p.n + qi[0]] = Sw[0];
+        J.ws.psum[((int64_t)it.seg * 2 + 1) * p.n + qi[0]] = Swz[0];
+    }
+    if (last_arrival(&J.sum_arrivals[it.tile], J.sp.segments) && qi[0] < p.n) {
+        double sw = 0.0, swz = 0.0;
+        for (int seg = 0; seg < J.sp.segments; ++seg) {
+            sw += J.ws.psum[((int64_t)seg * 2 + 0) * p.n + qi[0]];
+            swz += J.ws.psum[((int64_t)seg * 2 + 1) * p.n + qi[0]];
+        }
+        p.out[qi[0]] = (float)(swz / sw);
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(kGroupSize) void aidw_f32_serve(const ServeJob* __restrict__ jobs,
+                                                             const ServeItem* __restrict__ items,
+                                                             int n_items, int* __restrict__ counter) {
+    for (;;) {
+        int it = 0;
+        if (lane_id() == 0) it = atomicAdd(counter, 1);
+        it = __builtin_amdgcn_readfirstlane(it);
+        if (it >= n_items) break;
+        const ServeItem w = items[it];
+        serve_item<K>(jobs[w.job], w);
+    }
 }
 
 // ---- host-side launchers ----------------------------------------------------------
@@ -471,6 +562,23 @@ int batch_occupancy_k() {
     return blocks;
 }
 
+template <int K>
+hipError_t launch_serve_k(const ServeLaunch& sl, hipStream_t stream) {
+    hipLaunchKernelGGL(aidw_reset_counter, dim3(1), dim3(64), 0, stream, sl.counter);
+    hipLaunchKernelGGL((aidw_f32_serve<K>), dim3(sl.groups), dim3(kGroupSize), 0, stream, sl.jobs,
+                       sl.items, sl.n_items, sl.counter);
+    return hipGetLastError();
+}
+
+template <int K>
+int serve_occupancy_k() {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, aidw_f32_serve<K>, kGroupSize, 0) !=
+        hipSuccess)
+        return 0;
+    return blocks;
+}
+
 #define AIDW_K_DISPATCH(K_RUNTIME, CALL) \
     switch (K_RUNTIME) {                 \
         case 4: return CALL(4);          \
@@ -501,6 +609,21 @@ hipError_t launch_aidw_f32_batch(const BatchLaunch& b, hipStream_t stream) {
     AIDW_K_DISPATCH(b.K, CALL)
 #undef CALL
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_aidw_f32_serve(const ServeLaunch& sl, hipStream_t stream) {
+    if (sl.n_items <= 0) return hipSuccess;
+#define CALL(KK) launch_serve_k<KK>(sl, stream)
+    AIDW_K_DISPATCH(sl.K, CALL)
+#undef CALL
+    return hipErrorInvalidValue;
+}
+
+int serve_blocks_per_cu(int K) {
+#define CALL(KK) serve_occupancy_k<KK>()
+    AIDW_K_DISPATCH(K, CALL)
+#undef CALL
+    return 0;
 }
 
 int batch_blocks_per_cu(int K) {

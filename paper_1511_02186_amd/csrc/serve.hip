@@ -1,0 +1,455 @@
+// Serving loop of libaidw: registered data sets, job submission and
+// polling, and the HIP executor that turns each scheduling tick into one
+// launch of the serving kernel (declared in include/aidw.h).
+//
+// Threads: client threads call aidw_submit / aidw_poll / aidw_wait; one
+// worker thread per server runs the scheduler.  Every scheduler and executor
+// call happens under the server's mutex.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "handle.h"
+#include "serve_sched.h"
+
+using namespace aidw::detail;
+namespace sv = aidw::serve;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct JobRec {
+    aidw::ProblemF32 p{};
+    aidw::SplitPlan sp{};
+    int K = 4;
+    size_t ws_bytes = 0;        // split workspace, then the two arrival-counter arrays
+    size_t counters_off = 0;    // offset of the counters inside the job's workspace
+    char* ws = nullptr;         // device address of the job's workspace
+    bool counters_zeroed = false;
+    uint64_t dataset = 0;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool launched = false;
+    bool failed = false;
+    void* host = nullptr;  // pinned staging of the tick's jobs and items
+    size_t host_cap = 0;
+    void* dev = nullptr;
+    size_t dev_cap = 0;
+};
+
+class HipExecutor : public sv::Executor {
+   public:
+    aidw_t h = nullptr;
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    std::unordered_map<uint64_t, JobRec> jobs;
+    std::vector<Slot> slots;
+    int blocks_per_cu[33] = {0};
+    aidw_status error = AIDW_OK;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+    double now() override {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+
+    int admit(uint64_t t, size_t off) override {
+        JobRec& r = jobs[t];
+        if (r.sp.segments > 1) r.ws = arena + off;
+        return 0;
+    }
+
+    int launch(const sv::TickPlan& plan, int slot) override {
+        Slot& s = slots[(size_t)slot];
+        std::unordered_map<uint64_t, int> index;
+        std::vector<aidw::ServeJob> sj;
+        int K = 4;
+        for (uint64_t t : plan.jobs) {
+            JobRec& r = jobs[t];
+            index[t] = (int)sj.size();
+            aidw::ServeJob j{};
+            j.p = r.p;
+            j.sp = r.sp;
+            if (r.sp.segments > 1) {
+                split_workspace_bytes(r.sp, r.p.ap.k, r.p.n, &j.ws, r.ws);
+                j.knn_arrivals = reinterpret_cast<int*>(r.ws + r.counters_off);
+                j.sum_arrivals = j.knn_arrivals + r.sp.tiles;
+            }
+            sj.push_back(j);
+            K = std::max(K, r.K);
+        }
+        std::vector<aidw::ServeItem> items(plan.items.size());
+        for (size_t i = 0; i < plan.items.size(); ++i) {
+            const sv::Item& it = plan.items[i];
+            items[i] = aidw::ServeItem{index[it.ticket], it.phase, it.tile, it.seg};
+        }
+        const size_t b_jobs = align_up(sizeof(aidw::ServeJob) * sj.size());
+        const size_t b_items = align_up(sizeof(aidw::ServeItem) * items.size());
+        const size_t bytes = b_jobs + b_items + kAlign;
+        if (grow(s, bytes) != AIDW_OK) return AIDW_ENOMEM;
+        char* host = static_cast<char*>(s.host);
+        memcpy(host, sj.data(), sizeof(aidw::ServeJob) * sj.size());
+        memcpy(host + b_jobs, items.data(), sizeof(aidw::ServeItem) * items.size());
+        char* dev = static_cast<char*>(s.dev);
+        hipError_t e = hipMemcpyAsync(dev, host, b_jobs + b_items, hipMemcpyHostToDevice, s.stream);
+        // arrival counters start at zero before a split job's first item
+        for (uint64_t t : plan.jobs) {
+            JobRec& r = jobs[t];
+            if (e != hipSuccess || r.sp.segments <= 1 || r.counters_zeroed) continue;
+            e = hipMemsetAsync(r.ws + r.counters_off, 0, 2 * sizeof(int) * (size_t)r.sp.tiles,
+                               s.stream);
+            r.counters_zeroed = true;
+        }
+        if (e != hipSuccess) {
+            error = hip_fail(e, "tick upload");
+            return AIDW_EDEVICE;
+        }
+        aidw::ServeLaunch sl;
+        sl.jobs = reinterpret_cast<const aidw::ServeJob*>(dev);
+        sl.items = reinterpret_cast<const aidw::ServeItem*>(dev + b_jobs);
+        sl.counter = reinterpret_cast<int*>(dev + b_jobs + b_items);
+        sl.n_items = (int)items.size();
+        sl.K = aidw::k_bucket(K);
+        if (!blocks_per_cu[sl.K]) blocks_per_cu[sl.K] = std::max(1, aidw::serve_blocks_per_cu(sl.K));
+        const int64_t need = ((int64_t)items.size() + aidw::kWavesPerGroup - 1) / aidw::kWavesPerGroup;
+        sl.groups = (int)std::max<int64_t>(
+            1, std::min<int64_t>((int64_t)blocks_per_cu[sl.K] * h->cu_count, need));
+        e = aidw::launch_aidw_f32_serve(sl, s.stream);
+        if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
+        if (e != hipSuccess) {
+            error = hip_fail(e, "tick launch");
+            return AIDW_EDEVICE;
+        }
+        s.launched = true;
+        return 0;
+    }
+
+    bool done(int slot) override {
+        Slot& s = slots[(size_t)slot];
+        if (!s.launched) return true;
+        const hipError_t e = hipEventQuery(s.done);
+        if (e == hipErrorNotReady) return false;
+        if (e != hipSuccess) error = hip_fail(e, "tick completion");
+        s.launched = false;
+        return true;
+    }
+
+    void retire(uint64_t t, int) override {
+        auto it = jobs.find(t);
+        if (it == jobs.end()) return;
+        if (it->second.dataset) {
+            std::lock_guard<std::mutex> lk(h->mu);
+            auto d = h->datasets.find(it->second.dataset);
+            if (d != h->datasets.end()) --d->second.refs;
+        }
+        jobs.erase(it);
+    }
+
+   private:
+    aidw_status grow(Slot& s, size_t bytes) {
+        if (bytes > s.host_cap) {
+            if (s.host) (void)hipHostFree(s.host);
+            s.host = nullptr;
+            s.host_cap = 0;
+            if (hipHostMalloc(&s.host, bytes, hipHostMallocDefault) != hipSuccess) {
+                s.host = nullptr;
+                return fail(AIDW_ENOMEM, "pinned staging of %zu bytes", bytes);
+            }
+            s.host_cap = bytes;
+        }
+        if (bytes > s.dev_cap) {
+            device_free(h, s.dev, s.dev_cap);
+            s.dev = nullptr;
+            s.dev_cap = 0;
+            aidw_status st = device_alloc(h, bytes * 2, &s.dev);
+            if (st != AIDW_OK) return st;
+            s.dev_cap = bytes * 2;
+        }
+        return AIDW_OK;
+    }
+};
+
+aidw_status to_status(int rc) {
+    if (rc == 0) return AIDW_OK;
+    if (rc == -2) return AIDW_ENOMEM;
+    return rc < 0 ? (aidw_status)rc : AIDW_EDEVICE;
+}
+
+}  // namespace
+
+struct aidw_server {
+    aidw_t h = nullptr;
+    HipExecutor ex;
+    sv::Scheduler* sched = nullptr;
+    aidw_server_options opt{};
+    std::mutex mu;
+    std::condition_variable cv;
+    std::thread worker;
+    bool stop = false;
+
+    void run() {
+        (void)hipSetDevice(h->device);
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            const bool changed = sched->step();
+            if (stop && sched->idle()) break;
+            if (!changed) cv.wait_for(lk, std::chrono::microseconds(50));
+        }
+    }
+};
+
+extern "C" {
+
+aidw_status aidw_dataset_register(aidw_t h, const void* data_xy, const void* data_z, int64_t m,
+                                  double area, uint64_t* id) {
+    if (!h || !id) return fail(AIDW_EINVAL, "handle or id is NULL");
+    *id = 0;
+    if (m < 1 || m > INT32_MAX) return fail(AIDW_EINVAL, "m = %lld out of [1, 2^31-1]", (long long)m);
+    if (!std::isfinite(area) || area <= 0.0) return fail(AIDW_EINVAL, "area must be finite and > 0");
+    if (!data_xy || !data_z) return fail(AIDW_EINVAL, "NULL data pointer");
+    if ((uintptr_t)data_xy % 4 || (uintptr_t)data_z % 4)
+        return fail(AIDW_EINVAL, "pointer not aligned to 4 bytes");
+    const size_t bxy = align_up(2 * sizeof(float) * (size_t)m);
+    const size_t bytes = bxy + sizeof(float) * (size_t)m;
+    void* mem = nullptr;
+    aidw_status st = device_alloc(h, bytes, &mem);
+    if (st != AIDW_OK) return st;
+    char* base = static_cast<char*>(mem);
+    hipError_t e = hipMemcpyAsync(base, data_xy, 2 * sizeof(float) * (size_t)m,
+                                  hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + bxy, data_z, sizeof(float) * (size_t)m, hipMemcpyDeviceToDevice,
+                           h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        device_free(h, mem, bytes);
+        return hip_fail(e, "dataset copy");
+    }
+    std::lock_guard<std::mutex> lk(h->mu);
+    aidw_dataset_rec r;
+    r.xy = reinterpret_cast<float*>(base);
+    r.z = reinterpret_cast<float*>(base + bxy);
+    r.m = m;
+    r.area = area;
+    r.bytes = bytes;
+    *id = h->next_dataset++;
+    h->datasets[*id] = r;
+    return AIDW_OK;
+}
+
+aidw_status aidw_dataset_release(aidw_t h, uint64_t id) {
+    if (!h) return fail(AIDW_EINVAL, "handle is NULL");
+    aidw_dataset_rec r;
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        auto it = h->datasets.find(id);
+        if (it == h->datasets.end()) return fail(AIDW_ENOTFOUND, "no dataset %llu", (unsigned long long)id);
+        if (it->second.refs > 0)
+            return fail(AIDW_EAGAIN, "dataset %llu is read by %d unfinished jobs",
+                        (unsigned long long)id, it->second.refs);
+        r = it->second;
+        h->datasets.erase(it);
+    }
+    device_free(h, r.xy, r.bytes);
+    return AIDW_OK;
+}
+
+aidw_status aidw_server_create(aidw_t h, const aidw_server_options* opt, aidw_server_t* out) {
+    if (!h || !out) return fail(AIDW_EINVAL, "handle or out is NULL");
+    *out = nullptr;
+    aidw_server_options o{};
+    if (opt) o = *opt;
+    if (o.arena_bytes == 0) o.arena_bytes = (size_t)2 << 30;
+    if (o.streams <= 0) o.streams = 2;
+    if (o.tick_pair_evals <= 0) o.tick_pair_evals = 4e10;
+    if (o.max_wait_s <= 0) o.max_wait_s = 0.25;
+    if (o.segment_points <= 0) o.segment_points = 32768;
+    if (o.streams > 8) return fail(AIDW_EINVAL, "streams = %d > 8", o.streams);
+    aidw_server* s = new (std::nothrow) aidw_server;
+    if (!s) return fail(AIDW_ENOMEM, "host allocation failed");
+    s->h = h;
+    s->opt = o;
+    s->ex.h = h;
+    void* arena = nullptr;
+    aidw_status st = device_alloc(h, o.arena_bytes, &arena);
+    if (st != AIDW_OK) {
+        delete s;
+        return st;
+    }
+    s->ex.arena = static_cast<char*>(arena);
+    s->ex.arena_bytes = o.arena_bytes;
+    s->ex.slots.resize((size_t)o.streams);
+    for (Slot& sl : s->ex.slots) {
+        hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "stream or event creation");
+            aidw_server_destroy(s);
+            return st;
+        }
+    }
+    sv::Config cfg;
+    cfg.arena_bytes = o.arena_bytes;
+    cfg.slots = o.streams;
+    cfg.tick_pairs = o.tick_pair_evals;
+    cfg.max_wait_s = o.max_wait_s;
+    s->sched = new (std::nothrow) sv::Scheduler(&s->ex, cfg);
+    if (!s->sched) {
+        aidw_server_destroy(s);
+        return fail(AIDW_ENOMEM, "host allocation failed");
+    }
+    s->worker = std::thread([s] { s->run(); });
+    *out = s;
+    return AIDW_OK;
+}
+
+void aidw_server_destroy(aidw_server_t s) {
+    if (!s) return;
+    if (s->worker.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stop = true;
+        }
+        s->cv.notify_all();
+        s->worker.join();
+    }
+    for (Slot& sl : s->ex.slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        if (sl.host) (void)hipHostFree(sl.host);
+        device_free(s->h, sl.dev, sl.dev_cap);
+    }
+    device_free(s->h, s->ex.arena, s->ex.arena_bytes);
+    delete s->sched;
+    delete s;
+}
+
+aidw_status aidw_submit(aidw_server_t s, const aidw_job* job, uint64_t* ticket) {
+    if (!s || !job || !ticket) return fail(AIDW_EINVAL, "server, job or ticket is NULL");
+    *ticket = 0;
+    aidw_problem p;
+    memset(&p, 0, sizeof p);
+    p.precision = AIDW_FP32_SCALED;
+    p.data_xy = job->data_xy;
+    p.data_z = job->data_z;
+    p.m = job->m;
+    p.area = job->area;
+    aidw_t h = s->h;
+    if (job->dataset) {
+        std::lock_guard<std::mutex> lk(h->mu);
+        auto it = h->datasets.find(job->dataset);
+        if (it == h->datasets.end())
+            return fail(AIDW_ENOTFOUND, "no dataset %llu", (unsigned long long)job->dataset);
+        p.data_xy = it->second.xy;
+        p.data_z = it->second.z;
+        p.m = it->second.m;
+        p.area = it->second.area;
+    }
+    p.query_xy = job->query_xy;
+    p.n = job->n;
+    p.k = job->k;
+    for (int i = 0; i < 5; ++i) p.alpha_levels[i] = job->alpha_levels[i];
+    p.R_min = job->R_min;
+    p.R_max = job->R_max;
+    p.out = job->out;
+    p.r_obs = job->r_obs;
+    p.alpha = job->alpha;
+    aidw_status st = validate(&p);
+    if (st != AIDW_OK) return st;
+
+    JobRec r;
+    r.p = problem_f32(&p);
+    r.K = aidw::k_bucket(p.k);
+    r.sp = aidw::SplitPlan{1, (int)p.m, (int)((p.n + 63) / 64)};
+    sv::JobSpec spec;
+    spec.m = p.m;
+    spec.n = p.n;
+    const int64_t seg = (s->opt.segment_points + 31) / 32 * 32;
+    if (p.m > seg && p.n > 0) {
+        r.sp.seg_len = (int)seg;
+        r.sp.segments = (int)((p.m + seg - 1) / seg);
+        r.counters_off = align_up(split_workspace_bytes(r.sp, p.k, p.n, nullptr, nullptr));
+        r.ws_bytes = r.counters_off + 2 * sizeof(int) * (size_t)r.sp.tiles;
+        spec.segments = r.sp.segments;
+        spec.seg_len = seg;
+        spec.ws_bytes = r.ws_bytes;
+    }
+    r.dataset = job->dataset;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (job->dataset) {
+        std::lock_guard<std::mutex> lk2(h->mu);
+        auto it = h->datasets.find(job->dataset);
+        if (it == h->datasets.end())
+            return fail(AIDW_ENOTFOUND, "no dataset %llu", (unsigned long long)job->dataset);
+        ++it->second.refs;
+    }
+    const uint64_t t = s->sched->submit(spec);
+    sv::JobState state;
+    s->sched->poll(t, &state, nullptr, nullptr);
+    if (state == sv::JobState::Failed) {
+        s->ex.jobs[t] = r;
+        s->ex.retire(t, -2);  // drops the dataset reference
+    } else {
+        s->ex.jobs[t] = r;
+    }
+    *ticket = t;
+    s->cv.notify_one();
+    return AIDW_OK;
+}
+
+aidw_status aidw_poll(aidw_server_t s, uint64_t ticket, aidw_status* job_status,
+                      double* latency_s) {
+    if (!s) return fail(AIDW_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    sv::JobState state;
+    double lat = 0.0;
+    int rc = 0;
+    if (!s->sched->poll(ticket, &state, &lat, &rc))
+        return fail(AIDW_ENOTFOUND, "no ticket %llu", (unsigned long long)ticket);
+    if (state == sv::JobState::Queued || state == sv::JobState::Admitted) return AIDW_EAGAIN;
+    if (job_status) *job_status = to_status(rc);
+    if (latency_s) *latency_s = lat;
+    s->sched->forget(ticket);
+    return AIDW_OK;
+}
+
+aidw_status aidw_wait(aidw_server_t s, uint64_t ticket, double timeout_s, aidw_status* job_status,
+                      double* latency_s) {
+    const auto t_end = std::chrono::steady_clock::now() +
+                       std::chrono::duration<double>(timeout_s < 0 ? 1e9 : timeout_s);
+    for (;;) {
+        aidw_status st = aidw_poll(s, ticket, job_status, latency_s);
+        if (st != AIDW_EAGAIN) return st;
+        if (std::chrono::steady_clock::now() >= t_end) return AIDW_EAGAIN;
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+}
+
+aidw_status aidw_server_stats(aidw_server_t s, aidw_server_counters* out) {
+    if (!s || !out) return fail(AIDW_EINVAL, "server or out is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    const sv::Stats st = s->sched->stats();
+    out->submitted = st.submitted;
+    out->completed = st.completed;
+    out->failed = st.failed;
+    out->ticks = st.ticks;
+    out->pair_evals = st.pair_evals;
+    out->arena_in_use = st.arena_in_use;
+    out->queued = st.queued;
+    out->admitted = st.admitted;
+    return s->ex.error;
+}
+
+}  // extern "C"
