@@ -26,6 +26,41 @@ FLOP_PER_PAIR = 9.0          # pass 1: 6 FLOP, pass 2: 12 FLOP, mean 9
 PEAK_FP32_TFLOPS = 157.3     # 256 CU x 2.4 GHz x 128 lanes x 2 (FMA)
 
 
+KERNEL_SOURCES = ["paper_1511_02186_amd/csrc/kernels_f32.hip",
+                  "paper_1511_02186_amd/csrc/device_math.h",
+                  "paper_1511_02186_amd/csrc/common.h"]
+TRAFFIC_PROFILE = "profiles/aidw_f32_fused_paper_scale_m1048576_n1048576.md"
+
+
+def kernel_sources_sha256():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per fused launch from the committed rocprofv3 counters, or
+    None when they were taken on other kernel sources (or are missing)."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -36,7 +71,16 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=512,
                     help="queries of the workload timed on the CPU oracle")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--fp64", action="store_true", help="also time the plain FP64 kernel once")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip timing the plain FP64 kernel at the same size")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 512-problem batched launch")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-requests", type=int, default=400,
+                    help="requests of the Poisson serving run")
+    ap.add_argument("--ablation", action="store_true",
+                    help="also time the data-access designs (scalar / LDS-tiled / naive loads, "
+                         "SoA / AoaS) at the paper's sizes, end to end like its Table 1")
     ap.add_argument("--check", type=int, default=64,
                     help="queries checked against the oracle after timing (0 = none)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -113,7 +157,8 @@ def main():
                    "R_max": inst.R_max, "precision": "fp32_scaled",
                    "pair_evals_per_step": pairs},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": measured_traffic() if inst.m == inst.n == 1 << 20 else None,
                      "kernel": "aidw_f32_fused", "flop_per_pair_eval": FLOP_PER_PAIR},
         "step_ms": {"p10": float(np.percentile(per, 10)), "p50": float(np.median(per)),
                     "p90": float(np.percentile(per, 90)), "wall_s": wall},
@@ -133,7 +178,7 @@ def main():
         result["max_rel_err_vs_oracle"] = float(np.max(np.abs(got - want) / scale))
         result["checked_queries"] = int(args.check)
 
-    if args.fp64:
+    if not args.no_fp64:
         inst64 = workloads.paper_scale(m=args.m, n=args.n, dtype=np.float64)
         d64 = aidw.to_device(inst64, dev)
         o64 = torch.empty(inst64.n, dtype=torch.float64, device=dev)
@@ -147,6 +192,13 @@ def main():
         ms64 = e0.elapsed_time(e1)
         result["fp64_plain"] = {"ms": ms64, "pair_evals_per_s": pairs / (ms64 * 1e-3),
                                 "speedup_fp32_scaled_vs_fp64": ms64 / ms}
+
+    if args.ablation:
+        result["ablation"] = bench_ablation(ctx, torch, aidw, workloads)
+    if not args.no_batch:
+        result["batched"] = bench_batched(ctx, torch, aidw, workloads)
+    if not args.no_serve:
+        result["serving"] = bench_serving(ctx, torch, aidw, workloads, args.serve_requests)
 
     if not args.no_cpu:
         import oracle
@@ -167,6 +219,131 @@ def main():
 
     ctx.close()
     print(json.dumps(result), flush=True)
+
+
+def bench_ablation(ctx, torch, aidw, workloads, sizes=(10240, 51200, 102400, 512000, 1024000)):
+    """The paper's Table 1 axes on this GPU: m = n = N points in a square,
+    every data-access design and layout, plus the production launch.  Times
+    are kernel-only (HIP events) and end to end (pinned host -> device copy of
+    the inputs, kernel, device -> host copy of the output), as in Sec. 4."""
+    designs = [("production", None, None)] + [
+        ("%s_%s" % (a, l), ai, li)
+        for ai, a in enumerate(["scalar", "tiled", "naive"])
+        for li, l in enumerate(["soa", "aoas"])]
+    rows = []
+    for N in sizes:
+        inst = workloads.paper_scale(m=N, n=N, seed=7)
+        host = [torch.from_numpy(a).pin_memory() for a in
+                (inst.data_xy(), inst.data_z.copy(), inst.query_xy())]
+        out_h = torch.empty(N, dtype=torch.float32).pin_memory()
+        for name, acc, lay in designs:
+            print("bench: ablation N=%d %s" % (N, name), file=sys.stderr, flush=True)
+            dev = [h.to("cuda", non_blocking=True) for h in host]
+            out = torch.empty(N, device="cuda")
+            ctx.bind_current_stream()
+            p = ctx.problem(dev[0], dev[1], dev[2], inst.k, out, inst.levels, inst.R_min,
+                            inst.R_max, inst.area, flags=aidw.AIDW_FLAG_ASYNC)
+
+            def run():
+                if acc is None:
+                    aidw.check(aidw.aidw_interpolate_ex(ctx.h, p))
+                else:
+                    aidw.check(aidw.aidw_interpolate_variant(ctx.h, p, acc, lay))
+
+            run()
+            torch.cuda.synchronize()
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            e[0].record()
+            for d, h in zip(dev, host):
+                d.copy_(h, non_blocking=True)
+            e[1].record()
+            run()
+            e[2].record()
+            out_h.copy_(out, non_blocking=True)
+            e[3].record()
+            torch.cuda.synchronize()
+            kern = e[1].elapsed_time(e[2])
+            rows.append({"N": N, "design": name, "kernel_ms": kern,
+                         "end_to_end_ms": e[0].elapsed_time(e[3]),
+                         "pair_evals_per_s": 2.0 * N * N / (kern * 1e-3)})
+    return {"workload": "m = n = N uniform points in [0, 1000]^2, k = 15 (N as in the paper's "
+                        "Table 1, 1K = 1024)", "rows": rows}
+
+
+def bench_batched(ctx, torch, aidw, workloads):
+    """512 independent problems of uneven size in one graph-replayed launch."""
+    print("bench: batched launch (512 problems)", file=sys.stderr, flush=True)
+    insts = workloads.batched()
+    dev = []
+    for i in insts:
+        d = aidw.to_device(i)
+        dev.append((i, d, torch.empty(i.n, device="cuda")))
+    probs = [ctx.problem(d[0], d[1], d[2], i.k, o, i.levels, i.R_min, i.R_max, i.area)
+             for i, d, o in dev]
+    ctx.bind_current_stream()
+    b = aidw.aidw_batch_create(ctx.h, probs)
+    try:
+        aidw.check(aidw.aidw_batch_launch(b))
+        times = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            aidw.check(aidw.aidw_batch_launch(b, aidw.AIDW_FLAG_ASYNC))
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+    finally:
+        aidw.aidw_batch_destroy(b)
+    pairs = float(sum(i.pair_evals() for i in insts))
+    ms = float(np.median(times))
+    return {"workload": "512 problems, m log-uniform [1024, 65536], n log-uniform "
+                        "[1024, 32768], uniform or clustered, k in {8, 10, 15}",
+            "pair_evals": pairs, "ms": ms, "pair_evals_per_s": pairs / (ms * 1e-3),
+            "frac_fp32_peak": FLOP_PER_PAIR * pairs / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+            "launch": "hipGraph replay, median of 5"}
+
+
+def bench_serving(ctx, torch, aidw, workloads, count):
+    """Poisson arrivals at 2000 requests/s of jobs with m log-uniform in
+    [4096, 2^20] and n log-uniform in [256, 2^18]; 20 % reuse a data set."""
+    print("bench: serving run (%d requests)" % count, file=sys.stderr, flush=True)
+    reqs, specs = workloads.serving_stream(count=count)
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    data = {}
+    for i, (m, _, _) in enumerate(specs):
+        xy = torch.rand((2, m), device="cuda", generator=gen)
+        data[i] = (xy, (torch.sin(4 * xy[0]) * torch.cos(3 * xy[1])).contiguous())
+    jobs = []
+    for r in reqs:
+        q = torch.rand((2, r.n), device="cuda", generator=gen)
+        out = torch.empty(r.n, device="cuda")
+        xy, z = data[r.dataset]
+        jobs.append((q, out, aidw.make_job(q, r.k, out, data_xy=xy, data_z=z, area=1.0)))
+    torch.cuda.synchronize()
+    srv = aidw.aidw_server_create(ctx.h, arena_bytes=16 << 30)
+    try:
+        t0 = time.perf_counter()
+        tickets = []
+        for r, (_, _, spec) in zip(reqs, jobs):
+            delay = r.t_arrival - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(aidw.aidw_submit(srv, spec))
+        res = [aidw.aidw_wait(srv, t, 600.0) for t in tickets]
+        wall = time.perf_counter() - t0
+        _, stats = aidw.aidw_server_stats(srv)
+    finally:
+        aidw.aidw_server_destroy(srv)
+    ok = sum(1 for st, js, _ in res if st == aidw.AIDW_OK and js == aidw.AIDW_OK)
+    lat = np.array([l for _, _, l in res]) * 1e3
+    pairs = float(sum(2.0 * specs[r.dataset][0] * r.n for r in reqs))
+    span = reqs[-1].t_arrival
+    return {"workload": "Poisson 2000 req/s, m log-uniform [4096, 2^20], n log-uniform "
+                        "[256, 2^18], k in {8, 10, 15}, 20 % data-set reuse, uniform points",
+            "requests": count, "completed": ok, "wall_s": wall,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "pair_evals_per_s": pairs / wall, "offered_pair_evals_per_s": pairs / span,
+            "ticks": stats["ticks"]}
 
 
 if __name__ == "__main__":

@@ -76,7 +76,14 @@ typedef enum aidw_precision {
 } aidw_precision;
 
 /* Flags for aidw_problem.flags. */
-#define AIDW_FLAG_ASYNC 1u /* return once the work is queued on the stream */
+#define AIDW_FLAG_ASYNC 1u     /* return once the work is queued on the stream */
+#define AIDW_FLAG_GRID_KNN 2u  /* FP32-scaled: find the k nearest through a uniform grid
+                                  over the data (about 2 points per cell) instead of a
+                                  full scan; the k nearest distances, r_obs, alpha and
+                                  the output are bit-identical to the full scan's.
+                                  Pass 2 still sums over all m points.  Not with
+                                  knn_idx.  Uses about 14 m + 32 n bytes of library
+                                  workspace. */
 
 typedef struct aidw_options {
     int device;                        /* HIP device ordinal */
@@ -132,6 +139,35 @@ aidw_status aidw_interpolate(aidw_t h, const void* data_xy, const void* data_z, 
  * diagnostics (r_obs, alpha, kNN indices) and flags. */
 aidw_status aidw_interpolate_ex(aidw_t h, const aidw_problem* p);
 
+/* Standard IDW (Sec. 2.1, Eq. 1): every query uses the constant power
+ * `power` (finite, >= 0) over all m data points.  Fields of *p as in
+ * aidw_interpolate_ex; its k, alpha_levels, R_min, R_max and area are
+ * ignored.  Runs the same kernels with every level set to `power` and k = 1
+ * (the nearest distance, which the FP32-scaled weights are rescaled by);
+ * the optional r_obs output then holds the nearest distance and knn_idx
+ * (with k = 1) the nearest data index. */
+aidw_status aidw_idw(aidw_t h, const aidw_problem* p, double power);
+
+/* Data-access designs, for comparing the paper's implementation choices on
+ * this GPU (Sec. 3.1.3 data layouts; Sec. 3.2 naive and tiled versions).
+ * Every variant does the FP32-scaled arithmetic of aidw_interpolate_ex, one
+ * query per lane, and differs only in how data points reach the lanes. */
+typedef enum aidw_access {
+    AIDW_ACCESS_SCALAR = 0,  /* wave-uniform scalar loads (the production design) */
+    AIDW_ACCESS_TILED = 1,   /* 256-point tiles staged in LDS per workgroup */
+    AIDW_ACCESS_NAIVE = 2    /* one global load per lane per data point */
+} aidw_access;
+typedef enum aidw_layout {
+    AIDW_LAYOUT_SOA = 0,   /* x[], y[], z[] as given */
+    AIDW_LAYOUT_AOAS = 1   /* {x, y, z, pad} per point, 16-byte aligned, packed by the
+                              library into its workspace (16 m bytes) */
+} aidw_layout;
+
+/* One FP32-scaled problem with a given access design and layout.  Fields
+ * as in aidw_interpolate_ex (knn_idx must be NULL). */
+aidw_status aidw_interpolate_variant(aidw_t h, const aidw_problem* p, aidw_access access,
+                                     aidw_layout layout);
+
 /* Launch shape of the FP32-scaled kernels.  Zero fields mean "automatic". */
 typedef struct aidw_tuning {
     int q_per_lane;          /* queries owned by each lane: 1, 2 or 4 */
@@ -146,6 +182,23 @@ typedef struct aidw_tuning {
  * automatic choice).  Returns AIDW_EINVAL for values outside the ranges
  * above. */
 aidw_status aidw_set_tuning(aidw_t h, const aidw_tuning* t);
+
+/* Autotuner.  Times the candidate launch shapes (queries per lane 1/2/4,
+ * no split or the automatic number of data segments, half and twice it,
+ * occupancy cap none/4) of an FP32-scaled problem of m data points, n
+ * queries and this k on synthetic uniform points, within about budget_s
+ * seconds of GPU time, and records the fastest for the size class
+ * (floor(log2 m), floor(log2 n), k bucket).  While the handle's tuning is
+ * all automatic, later calls in that class use the recorded shape.
+ * *best (may be NULL) receives it.  Uses about 12 (m + n) bytes of
+ * temporary device memory. */
+aidw_status aidw_tune(aidw_t h, int64_t m, int64_t n, int k, double budget_s, aidw_tuning* best);
+/* Write the handle's tuning table to `path` as JSON. */
+aidw_status aidw_tune_save(aidw_t h, const char* path);
+/* Replace the handle's tuning table by the one in `path` (written by
+ * aidw_tune_save).  AIDW_ENOTFOUND if it cannot be read, AIDW_EINVAL if it
+ * is not a tuning file or holds an invalid entry (the table is unchanged). */
+aidw_status aidw_tune_load(aidw_t h, const char* path);
 
 /* ---- Batches: many independent problems in one launch ----------------------
  * Every problem must be AIDW_FP32_SCALED and may not request knn_idx.  The

@@ -25,6 +25,13 @@ AIDW_FP32_SCALED = 0
 AIDW_FP64 = 1
 
 AIDW_FLAG_ASYNC = 1
+AIDW_FLAG_GRID_KNN = 2
+
+AIDW_ACCESS_SCALAR = 0
+AIDW_ACCESS_TILED = 1
+AIDW_ACCESS_NAIVE = 2
+AIDW_LAYOUT_SOA = 0
+AIDW_LAYOUT_AOAS = 1
 AIDW_KMAX = 32
 
 
@@ -110,6 +117,13 @@ _SIGNATURES = {
                                         ctypes.c_void_p]),
     "aidw_interpolate_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem)]),
     "aidw_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_tuning)]),
+    "aidw_idw": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem), ctypes.c_double]),
+    "aidw_interpolate_variant": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem),
+                                                ctypes.c_int, ctypes.c_int]),
+    "aidw_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                 ctypes.c_double, ctypes.POINTER(aidw_tuning)]),
+    "aidw_tune_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
+    "aidw_tune_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "aidw_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
     "aidw_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem), ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_void_p)]),
@@ -193,6 +207,29 @@ def aidw_interpolate(h, data_xy_ptr, data_z_ptr, m, query_xy_ptr, n, k, alpha_le
 
 def aidw_interpolate_ex(h, problem: aidw_problem) -> int:
     return lib().aidw_interpolate_ex(h, ctypes.byref(problem))
+
+
+def aidw_idw(h, problem: aidw_problem, power: float) -> int:
+    return lib().aidw_idw(h, ctypes.byref(problem), float(power))
+
+
+def aidw_interpolate_variant(h, problem: aidw_problem, access: int, layout: int) -> int:
+    return lib().aidw_interpolate_variant(h, ctypes.byref(problem), int(access), int(layout))
+
+
+def aidw_tune(h, m, n, k, budget_s=10.0):
+    t = aidw_tuning()
+    check(lib().aidw_tune(h, int(m), int(n), int(k), float(budget_s), ctypes.byref(t)))
+    return {"q_per_lane": t.q_per_lane, "max_waves_per_simd": t.max_waves_per_simd,
+            "split_segments": t.split_segments}
+
+
+def aidw_tune_save(h, path) -> int:
+    return lib().aidw_tune_save(h, str(path).encode())
+
+
+def aidw_tune_load(h, path) -> int:
+    return lib().aidw_tune_load(h, str(path).encode())
 
 
 def aidw_set_tuning(h, q_per_lane: int = 0, max_waves_per_simd: int = 0,
@@ -406,6 +443,19 @@ def make_job(query_xy, k, out, alpha_levels=(1, 2, 3, 4, 5), R_min=0.0, R_max=2.
     j.r_obs = r_obs.data_ptr() if r_obs is not None else None
     j.alpha = alpha.data_ptr() if alpha is not None else None
     return j
+
+
+def idw(ctx, data_xy, data_z, query_xy, power, out=None):
+    """Standard IDW (constant power) over torch tensors on the GPU."""
+    import torch
+
+    n = query_xy.shape[-1]
+    if out is None:
+        out = torch.empty(n, dtype=data_xy.dtype, device=data_xy.device)
+    ctx.bind_current_stream()
+    p = ctx.problem(data_xy, data_z, query_xy, 1, out, area=1.0)
+    check(aidw_idw(ctx.h, p, power))
+    return out
 
 
 def to_device(inst, device="cuda"):

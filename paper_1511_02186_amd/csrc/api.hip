@@ -163,21 +163,26 @@ aidw_status ensure_workspace(aidw_t h, size_t bytes) {
     return st;
 }
 
+}  // namespace
+
+namespace aidw {
+namespace detail {
+
 // Number of data segments for an FP32-scaled problem: enough (tile, segment)
 // waves to give every SIMD about 8 resident waves, with segments of at least
 // kMinSegment points.  1 means the fused kernel.
 constexpr int kMinSegment = 2048;
 
-aidw::SplitPlan split_plan(const aidw_ctx* h, int64_t m, int64_t n) {
+aidw::SplitPlan split_plan_for(const aidw_ctx* h, const aidw_tuning& t, int64_t m, int64_t n) {
     aidw::SplitPlan sp{1, (int)m, (int)((n + aidw::kWaveSize - 1) / aidw::kWaveSize)};
-    int want = h->tuning.split_segments;
+    int want = t.split_segments;
     if (want == 0) {
         const int64_t target = (int64_t)(h->cu_count > 0 ? h->cu_count : 256) * 4 * 8;
         if (sp.tiles >= target) return sp;
         want = (int)std::min<int64_t>((target + sp.tiles - 1) / sp.tiles, 1 << 20);
     }
     int64_t seg = (m + want - 1) / want;
-    if (h->tuning.split_segments == 0) seg = std::max<int64_t>(seg, kMinSegment);
+    if (t.split_segments == 0) seg = std::max<int64_t>(seg, kMinSegment);
     seg = (seg + 31) / 32 * 32;  // whole scalar-load batches
     if (seg >= m) return sp;
     sp.seg_len = (int)seg;
@@ -185,15 +190,10 @@ aidw::SplitPlan split_plan(const aidw_ctx* h, int64_t m, int64_t n) {
     return sp;
 }
 
-}  // namespace
-
-namespace aidw {
-namespace detail {
-
 size_t split_workspace_bytes(const aidw::SplitPlan& sp, int k, int64_t n, aidw::SplitWorkspace* ws,
                              char* base) {
     const size_t part = (size_t)sp.segments * k * n * sizeof(float);
-    const size_t qpar = 2 * (size_t)n * sizeof(float);
+    const size_t qpar = 4 * (size_t)n * sizeof(float);
     const size_t psum = (size_t)sp.segments * 2 * n * sizeof(double);
     const size_t a = 256;
     const size_t o_qpar = (part + a - 1) / a * a;
@@ -220,6 +220,47 @@ aidw::ProblemF32 problem_f32(const aidw_problem* p) {
 
 namespace {
 
+// Pass 1 through the uniform grid, then pass 2 over all points.
+hipError_t run_grid(aidw_t h, const aidw_problem* p, aidw_status* st_out) {
+    const int m = (int)p->m, n = (int)p->n;
+    const aidw::ProblemF32 q = problem_f32(p);
+    aidw::GridWorkspace gw{};
+    gw.cells = aidw::grid_cells(m);
+    gw.nparts = (int)std::min<int64_t>(1024, ((int64_t)m + 255) / 256);
+    gw.temp_bytes = aidw::grid_temp_bytes(gw.cells);
+    const size_t cells = (size_t)gw.cells;
+    // pass 2 split over data segments when there are too few queries to fill the chip
+    const aidw::SplitPlan sp = split_plan_for(h, h->tuning, m, n);
+    const size_t a = 256;
+    auto up = [&](size_t v) { return (v + a - 1) / a * a; };
+    size_t off[9], bytes = 0;
+    const size_t sizes[9] = {sizeof(aidw::GridGeom), sizeof(float4) * (size_t)gw.nparts,
+                             sizeof(int) * (cells + 1), sizeof(int) * (cells + 1),
+                             sizeof(int) * cells, sizeof(float2) * (size_t)m, gw.temp_bytes,
+                             4 * sizeof(float) * (size_t)n,
+                             2 * sizeof(double) * (size_t)n * (size_t)sp.segments};
+    for (int i = 0; i < 9; ++i) {
+        off[i] = bytes;
+        bytes += up(sizes[i]);
+    }
+    *st_out = ensure_workspace(h, bytes);
+    if (*st_out != AIDW_OK) return hipSuccess;
+    char* w = static_cast<char*>(h->workspace);
+    gw.geo = reinterpret_cast<aidw::GridGeom*>(w + off[0]);
+    gw.part = reinterpret_cast<float4*>(w + off[1]);
+    gw.counts = reinterpret_cast<int*>(w + off[2]);
+    gw.start = reinterpret_cast<int*>(w + off[3]);
+    gw.cursor = reinterpret_cast<int*>(w + off[4]);
+    gw.sorted = reinterpret_cast<float2*>(w + off[5]);
+    gw.temp = w + off[6];
+    gw.qpar = reinterpret_cast<float*>(w + off[7]);
+    gw.psum = reinterpret_cast<double*>(w + off[8]);
+    hipError_t e = aidw::launch_grid_knn_all(q, gw, h->stream);
+    if (e == hipSuccess) e = aidw::launch_aidw_f32_pass2(q, sp, gw.qpar, gw.psum, h->stream);
+    return e;
+}
+
+
 aidw_status run_problem(aidw_t h, const aidw_problem* p) {
     aidw_status st = validate(p);
     if (st != AIDW_OK) return st;
@@ -227,13 +268,25 @@ aidw_status run_problem(aidw_t h, const aidw_problem* p) {
     const aidw::AlphaParams ap = alpha_params(p);
     hipError_t e;
     const int m = (int)p->m, n = (int)p->n;
-    if (p->precision == AIDW_FP32_SCALED) {
+    if (p->flags & AIDW_FLAG_GRID_KNN) {
+        if (p->precision != AIDW_FP32_SCALED)
+            return fail(AIDW_EINVAL, "AIDW_FLAG_GRID_KNN needs the FP32-scaled precision");
+        if (p->knn_idx) return fail(AIDW_EINVAL, "AIDW_FLAG_GRID_KNN does not produce knn_idx");
+        aidw_status gst = AIDW_OK;
+        e = run_grid(h, p, &gst);
+        if (gst != AIDW_OK) return gst;
+    } else if (p->precision == AIDW_FP32_SCALED) {
         const aidw::ProblemF32 q = problem_f32(p);
-        aidw::LaunchF32 cfg{h->tuning.q_per_lane ? h->tuning.q_per_lane : default_q_per_lane(h, n),
-                            h->tuning.max_waves_per_simd};
+        aidw_tuning t = h->tuning;
+        aidw_tuning tuned;
+        if (!t.q_per_lane && !t.max_waves_per_simd && !t.split_segments &&
+            tuned_shape(h, m, n, p->k, &tuned))
+            t = tuned;
+        aidw::LaunchF32 cfg{t.q_per_lane ? t.q_per_lane : default_q_per_lane(h, n),
+                            t.max_waves_per_simd};
         aidw::SplitPlan sp{1, m, 0};
         aidw::SplitWorkspace ws{};
-        if (!p->knn_idx) sp = split_plan(h, m, n);
+        if (!p->knn_idx) sp = split_plan_for(h, t, m, n);
         if (sp.segments > 1) {
             aidw_status st = ensure_workspace(h, split_workspace_bytes(sp, p->k, n, nullptr, nullptr));
             if (st != AIDW_OK) return st;
@@ -331,6 +384,47 @@ aidw_status aidw_interpolate(aidw_t h, const void* data_xy, const void* data_z, 
 aidw_status aidw_interpolate_ex(aidw_t h, const aidw_problem* p) {
     if (!h) return fail(AIDW_EINVAL, "handle is NULL");
     return run_problem(h, p);
+}
+
+aidw_status aidw_idw(aidw_t h, const aidw_problem* p, double power) {
+    if (!h) return fail(AIDW_EINVAL, "handle is NULL");
+    if (!p) return fail(AIDW_EINVAL, "problem is NULL");
+    if (!std::isfinite(power) || power < 0.0)
+        return fail(AIDW_EINVAL, "power must be finite and >= 0");
+    aidw_problem q = *p;
+    q.k = 1;
+    for (int j = 0; j < 5; ++j) q.alpha_levels[j] = power;
+    q.R_min = 0.0;
+    q.R_max = 1.0;
+    q.area = 1.0;
+    return run_problem(h, &q);
+}
+
+aidw_status aidw_interpolate_variant(aidw_t h, const aidw_problem* p, aidw_access access,
+                                     aidw_layout layout) {
+    if (!h) return fail(AIDW_EINVAL, "handle is NULL");
+    aidw_status st = validate(p);
+    if (st != AIDW_OK) return st;
+    if (p->precision != AIDW_FP32_SCALED)
+        return fail(AIDW_EINVAL, "access variants are FP32-scaled only");
+    if (p->knn_idx) return fail(AIDW_EINVAL, "access variants do not produce knn_idx");
+    if ((int)access < 0 || (int)access > 2) return fail(AIDW_EINVAL, "unknown access %d", (int)access);
+    if ((int)layout < 0 || (int)layout > 1) return fail(AIDW_EINVAL, "unknown layout %d", (int)layout);
+    if (p->n == 0) return AIDW_OK;
+    float4* aos = nullptr;
+    if (layout == AIDW_LAYOUT_AOAS) {
+        st = ensure_workspace(h, sizeof(float4) * (size_t)p->m);
+        if (st != AIDW_OK) return st;
+        aos = static_cast<float4*>(h->workspace);
+    }
+    hipError_t e = aidw::launch_aidw_f32_variant(problem_f32(p), (int)access, (int)layout, aos,
+                                                 h->stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    if (!(p->flags & AIDW_FLAG_ASYNC)) {
+        e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    }
+    return AIDW_OK;
 }
 
 aidw_status aidw_set_tuning(aidw_t h, const aidw_tuning* t) {

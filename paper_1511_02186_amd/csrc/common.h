@@ -79,7 +79,8 @@ struct SplitPlan {
 // Device workspace of a split launch (sizes in split_workspace_bytes).
 struct SplitWorkspace {
     float* part;   // [segments][k][n] per-segment k nearest squared distances
-    float* qpar;   // [2][n] pass-2 exponent terms per query
+    float* qpar;   // [4][n] per query: -alpha/2, (alpha/2) log2 d_min^2, d_min,
+                   // and the whole power of the one-transcendental pass 2 (0: none)
     double* psum;  // [segments][2][n] per-segment sum w and sum w z
 };
 
@@ -131,6 +132,38 @@ struct ServeLaunch {
 };
 
 hipError_t launch_aidw_f32_serve(const ServeLaunch& s, hipStream_t stream);
+
+// ---- k nearest through a uniform grid (pass 1 without the full scan) -------
+struct GridGeom {
+    int gx, gy;         // gx x gy cells over the data's bounding box
+    float x0, y0;       // lower corner
+    float cw, ch;       // cell width and height
+    float inv_cw, inv_ch;
+};
+
+struct GridWorkspace {
+    GridGeom* geo;
+    float4* part;       // [nparts] partial bounding boxes
+    int nparts;
+    int cells;          // cap on gx * gy, fixed on the host
+    int* counts;        // [cells + 1]
+    int* start;         // [cells + 1] exclusive prefix sums of counts
+    int* cursor;        // [cells]
+    float2* sorted;     // [m] points ordered by cell
+    void* temp;         // scan scratch
+    size_t temp_bytes;
+    float* qpar;        // [4][n] as in SplitWorkspace
+    double* psum;       // [segments][2][n]
+};
+
+int grid_cells(int64_t m);
+size_t grid_temp_bytes(int cells);
+// Build the grid and write each query's pass-2 terms (and r_obs / alpha).
+hipError_t launch_grid_knn_all(const ProblemF32& p, const GridWorkspace& ws, hipStream_t s);
+// Pass 2 over all m points from precomputed per-query terms (qpar), then the
+// ratio: the split path's pass-2 kernels (sp.tiles is set here).
+hipError_t launch_aidw_f32_pass2(const ProblemF32& p, SplitPlan sp, const float* qpar,
+                                 double* psum, hipStream_t stream);
 int serve_blocks_per_cu(int K);
 
 hipError_t launch_aidw_f32(const ProblemF32& p, const LaunchF32& cfg, const SplitPlan* sp,
@@ -139,5 +172,9 @@ hipError_t launch_aidw_f32_batch(const BatchLaunch& b, hipStream_t stream);
 // Resident workgroups per CU of the batched kernel for register bucket K.
 int batch_blocks_per_cu(int K);
 hipError_t launch_aidw_f64(const ProblemF64& p, hipStream_t stream);
+// Data-access variants (0 scalar, 1 LDS tiles, 2 per-lane loads) x layouts
+// (0 SoA, 1 AoaS packed into `aos`, m float4), same arithmetic.
+hipError_t launch_aidw_f32_variant(const ProblemF32& p, int access, int layout, float4* aos,
+                                   hipStream_t stream);
 
 }  // namespace aidw

@@ -83,4 +83,34 @@ __device__ __forceinline__ void list_insert_idx(T (&t)[K], int (&ti)[K], T v, in
     }
 }
 
+// Squared distance in FP32, the one formula every FP32 kernel uses so that
+// their k-nearest lists agree bit for bit.
+__device__ __forceinline__ float sqdist(float qx, float qy, float px, float py) {
+    const float ex = qx - px;
+    const float ey = qy - py;
+    return fmaf(ey, ey, ex * ex);
+}
+
+// Per-query terms of pass 2 from the k-nearest list: alpha (Eq. 3-6), and for
+// w = exp2(na * log2 d^2 + aL0) = (d_min^2 / d^2)^(alpha/2), na = -alpha/2 and
+// aL0 = (alpha/2) log2 d_min^2.
+template <int K>
+__device__ __forceinline__ void query_power(const float (&top)[K], const AlphaParams& ap,
+                                            double& r_obs, double& al, float& na, float& aL0,
+                                            float& d2min) {
+    al = alpha_from_list<K, float>(top, ap, r_obs);
+    const float a = (float)(0.5 * al);
+    d2min = list_min<K, float>(top, ap.k);
+    const float L0 = __builtin_amdgcn_logf(d2min);
+    na = -a;
+    aL0 = a * L0;
+}
+
+// alpha as a small whole power (1..8) when the weights can be formed as
+// (d_min / d)^alpha with one reciprocal square root per pair; 0 otherwise.
+__device__ __forceinline__ int integer_power(double alpha, float d2min) {
+    const bool whole = alpha >= 1.0 && alpha <= 8.0 && alpha == (double)(int)alpha;
+    return (whole && d2min >= 1.17549435e-38f) ? (int)alpha : 0;
+}
+
 }  // namespace aidw

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <mutex>
 #include <unordered_map>
+#include <vector>
 
 #include "../../include/aidw.h"
 #include "common.h"
@@ -18,6 +19,13 @@ struct aidw_dataset_rec {
     double area = 0.0;
     size_t bytes = 0;
     int refs = 0;         // jobs in flight that read it
+};
+
+// Fastest launch shape measured for a size class (aidw_tune).
+struct TuneEntry {
+    int m_log2, n_log2, K;
+    aidw_tuning shape;
+    double ms;
 };
 
 struct aidw_ctx {
@@ -35,6 +43,7 @@ struct aidw_ctx {
     std::mutex mu;
     std::unordered_map<uint64_t, aidw_dataset_rec> datasets;
     uint64_t next_dataset = 1;
+    std::vector<TuneEntry> tune_table;  // consulted when `tuning` is all automatic
 };
 
 namespace aidw {
@@ -50,6 +59,11 @@ void device_free(aidw_t h, void* p, size_t bytes);
 // Bytes of a split workspace; with ws/base given, also lays it out at base.
 size_t split_workspace_bytes(const SplitPlan& sp, int k, int64_t n, SplitWorkspace* ws,
                              char* base);
+// Data segments of a problem under launch shape t (t.split_segments: 0
+// automatic, 1 never split, S forced).
+SplitPlan split_plan_for(const aidw_ctx* h, const aidw_tuning& t, int64_t m, int64_t n);
+// The tuned shape of the size class of (m, n, k), if aidw_tune measured one.
+bool tuned_shape(const aidw_ctx* h, int64_t m, int64_t n, int k, aidw_tuning* out);
 
 }  // namespace detail
 }  // namespace aidw

@@ -61,11 +61,6 @@ constexpr int batch1_for() { return Q == 1 ? AIDW_F32_B1 : 16; }
 template <int Q>
 constexpr int batch2_for() { return Q == 1 ? AIDW_F32_B2 : 16; }
 
-__device__ __forceinline__ float sqdist(float qx, float qy, float px, float py) {
-    const float ex = qx - px;
-    const float ey = qy - py;
-    return fmaf(ey, ey, ex * ex);
-}
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWaveSize - 1); }
 
@@ -153,18 +148,6 @@ __device__ __forceinline__ void init_lists(float (&top)[Q][K],
         }
 }
 
-// alpha of one query (Eq. 2-6) and its pass-2 exponent terms: weights are
-// exp2(na * log2(d^2) + aL0) with na = -alpha/2, aL0 = (alpha/2) log2(d_min^2).
-template <int K>
-__device__ __forceinline__ void query_power(const float (&top)[K], const AlphaParams& ap,
-                                            double& r_obs, double& al, float& na, float& aL0) {
-    al = alpha_from_list<K, float>(top, ap, r_obs);
-    const float a = (float)(0.5 * al);
-    const float L0 = __builtin_amdgcn_logf(list_min<K, float>(top, ap.k));
-    na = -a;
-    aL0 = a * L0;
-}
-
 // True when the query coincides with a data point: log2(d_min^2) = -inf makes
 // aL0 -inf (alpha > 0) or NaN (alpha = 0).
 __device__ __forceinline__ bool coincident(float aL0) { return !(aL0 > -INFINITY); }
@@ -215,11 +198,76 @@ __device__ __forceinline__ void scan_wsum(cptr X, cptr Y, cptr Z, int j0, int j1
     }
 }
 
+// s^A for a compile-time integer A, by repeated squaring.
+template <int A>
+__device__ __forceinline__ float ipow(float s) {
+    if constexpr (A == 1) return s;
+    else if constexpr (A % 2 == 0) {
+        const float h = ipow<A / 2>(s);
+        return h * h;
+    } else {
+        return ipow<A - 1>(s) * s;
+    }
+}
+
+// Pass 2 for a wave whose queries all have the same integer power A and a
+// normal, nonzero d_min: w = (d_min / d)^A = (d_min * rsq(d^2))^A, one
+// transcendental instead of two.
+template <int A>
+__device__ __forceinline__ void scan_wsum_int(cptr X, cptr Y, cptr Z, int j0, int j1, float qx,
+                                              float qy, float dmin, double& Sw, double& Swz) {
+    constexpr int B = batch2_for<1>();
+    int j = j0;
+    for (; j + B <= j1; j += B) {
+        float px[B], py[B], pz[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            px[u] = X[j + u];
+            py[u] = Y[j + u];
+            pz[u] = Z[j + u];
+        }
+        float sw = 0.0f, swz = 0.0f;
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const float w = ipow<A>(dmin * __builtin_amdgcn_rsqf(sqdist(qx, qy, px[u], py[u])));
+            sw += w;
+            swz = fmaf(w, pz[u], swz);
+        }
+        Sw += (double)sw;
+        Swz += (double)swz;
+    }
+    for (; j < j1; ++j) {
+        const float w = ipow<A>(dmin * __builtin_amdgcn_rsqf(sqdist(qx, qy, X[j], Y[j])));
+        Sw += (double)w;
+        Swz += (double)(w * Z[j]);
+    }
+}
+
+// Pass 2 for one lane's queries: the whole-power loop when every lane of the
+// wave has the same integer power (see integer_power), else the exp2/log2 one.
 template <int Q>
 __device__ __forceinline__ void scan_wsum_any(cptr X, cptr Y, cptr Z, int j0, int j1,
                                               const float (&qx)[Q], const float (&qy)[Q],
                                               const float (&na)[Q], const float (&aL0)[Q],
-                                              double (&Sw)[Q], double (&Swz)[Q]) {
+                                              double (&Sw)[Q], double (&Swz)[Q],
+                                              int ipw = 0, float dmin = 0.0f) {
+    if constexpr (Q == 1) {
+        // same whole power in every lane: the one-transcendental loop
+        const int a0 = __builtin_amdgcn_readfirstlane(ipw);
+        if (a0 != 0 && __all(ipw == a0)) {
+            switch (a0) {
+                case 1: return scan_wsum_int<1>(X, Y, Z, j0, j1, qx[0], qy[0], dmin, Sw[0], Swz[0]);
+                case 2: return scan_wsum_int<2>(X, Y, Z, j0, j1, qx[0], qy[0], dmin, Sw[0], Swz[0]);
+                case 3: return scan_wsum_int<3>(X, Y, Z, j0, j1, qx[0], qy[0], dmin, Sw[0], Swz[0]);
+                case 4: return scan_wsum_int<4>(X, Y, Z, j0, j1, qx[0], qy[0], dmin, Sw[0], Swz[0]);
+                case 5: return scan_wsum_int<5>(X, Y, Z, j0, j1, qx[0], qy[0], dmin, Sw[0], Swz[0]);
+                case 6: return scan_wsum_int<6>(X, Y, Z, j0, j1, qx[0], qy[0], dmin, Sw[0], Swz[0]);
+                case 7: return scan_wsum_int<7>(X, Y, Z, j0, j1, qx[0], qy[0], dmin, Sw[0], Swz[0]);
+                case 8: return scan_wsum_int<8>(X, Y, Z, j0, j1, qx[0], qy[0], dmin, Sw[0], Swz[0]);
+                default: break;
+            }
+        }
+    }
     bool any_coincident = false;
 #pragma unroll
     for (int s = 0; s < Q; ++s) any_coincident |= coincident(aL0[s]);
@@ -255,11 +303,13 @@ __device__ __forceinline__ void fused_tile(const ProblemF32& p, int base) {
     scan_knn<K, Q, TRACK>(as_const(p.dx), as_const(p.dy), 0, p.m, qx, qy, top, tix);
 
     const int pad = K - p.ap.k;
-    float na[Q], aL0[Q];
+    float na[Q], aL0[Q], d2min[Q];
+    int ipw = 0;
 #pragma unroll
     for (int s = 0; s < Q; ++s) {
         double r_obs, al;
-        query_power<K>(top[s], p.ap, r_obs, al, na[s], aL0[s]);
+        query_power<K>(top[s], p.ap, r_obs, al, na[s], aL0[s], d2min[s]);
+        if (Q == 1) ipw = integer_power(al, d2min[s]);
         if (qi[s] < p.n) {
             if (p.r_obs) p.r_obs[qi[s]] = r_obs;
             if (p.alpha) p.alpha[qi[s]] = al;
@@ -275,7 +325,7 @@ __device__ __forceinline__ void fused_tile(const ProblemF32& p, int base) {
 #pragma unroll
     for (int s = 0; s < Q; ++s) Sw[s] = Swz[s] = 0.0;
     scan_wsum_any<Q>(as_const(p.dx), as_const(p.dy), as_const(p.dz), 0, p.m, qx, qy, na, aL0, Sw,
-                     Swz);
+                     Swz, ipw, sqrtf(d2min[0]));
 
 #pragma unroll
     for (int s = 0; s < Q; ++s)
@@ -336,10 +386,12 @@ __device__ __forceinline__ void merge_tile(const ProblemF32& p, const SplitPlan&
         }
     }
     double r_obs, al;
-    float na, aL0;
-    query_power<K>(top[0], p.ap, r_obs, al, na, aL0);
+    float na, aL0, d2min;
+    query_power<K>(top[0], p.ap, r_obs, al, na, aL0, d2min);
     qpar[q] = na;
     qpar[p.n + q] = aL0;
+    qpar[2 * p.n + q] = sqrtf(d2min);
+    qpar[3 * p.n + q] = (float)integer_power(al, d2min);
     if (p.r_obs) p.r_obs[q] = r_obs;
     if (p.alpha) p.alpha[q] = al;
 }
@@ -393,7 +445,7 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_wsum_part(ProblemF32 p, S
     float na[1] = {qpar[c]}, aL0[1] = {qpar[p.n + c]};
     double Sw[1] = {0.0}, Swz[1] = {0.0};
     scan_wsum_any<1>(as_const(p.dx), as_const(p.dy), as_const(p.dz), j0, j1, qx, qy, na, aL0, Sw,
-                     Swz);
+                     Swz, (int)qpar[3 * p.n + c], qpar[2 * p.n + c]);
     if (qi[0] < p.n) {
         psum[((int64_t)seg * 2 + 0) * p.n + qi[0]] = Sw[0];
         psum[((int64_t)seg * 2 + 1) * p.n + qi[0]] = Swz[0];
@@ -457,7 +509,7 @@ __device__ __forceinline__ void serve_item(const ServeJob& J, const ServeItem& i
     float na[1] = {J.ws.qpar[c]}, aL0[1] = {J.ws.qpar[p.n + c]};
     double Sw[1] = {0.0}, Swz[1] = {0.0};
     scan_wsum_any<1>(as_const(p.dx), as_const(p.dy), as_const(p.dz), j0, j1, qx, qy, na, aL0, Sw,
-                     Swz);
+                     Swz, (int)J.ws.qpar[3 * p.n + c], J.ws.qpar[2 * p.n + c]);
     if (qi[0] < p.n) {
         J.ws.psum[((int64_t)it.seg * 2 + 0) * p.n + qi[0]] = Sw[0];
         J.ws.psum[((int64_t)it.seg * 2 + 1) * p.n + qi[0]] = Swz[0];
@@ -601,6 +653,17 @@ hipError_t launch_aidw_f32(const ProblemF32& p, const LaunchF32& cfg, const Spli
     AIDW_K_DISPATCH(k_bucket(p.ap.k), CALL)
 #undef CALL
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_aidw_f32_pass2(const ProblemF32& p, SplitPlan sp, const float* qpar,
+                                 double* psum, hipStream_t stream) {
+    if (p.n <= 0) return hipSuccess;
+    sp.tiles = (int)((p.n + kWaveSize - 1) / kWaveSize);
+    hipLaunchKernelGGL(aidw_f32_wsum_part, dim3(groups_for((int64_t)sp.segments * sp.tiles)),
+                       dim3(kGroupSize), 0, stream, p, sp, qpar, psum);
+    hipLaunchKernelGGL(aidw_f32_wsum_reduce, dim3((unsigned)((p.n + kGroupSize - 1) / kGroupSize)),
+                       dim3(kGroupSize), 0, stream, p, sp, psum);
+    return hipGetLastError();
 }
 
 hipError_t launch_aidw_f32_batch(const BatchLaunch& b, hipStream_t stream) {

@@ -111,8 +111,9 @@ def test_fp32_launch_shapes_agree(ctx, torch, q):
     inst = workloads.paper_scale(m=3001, n=2 * 4 * 256 + 77, seed=21)
     out = gpu_run(ctx, torch, inst, q_per_lane=q)
     base = gpu_run(ctx, torch, inst, q_per_lane=1)
-    # the per-query arithmetic does not depend on the slot a query occupies
-    assert np.array_equal(out, base)
+    # one query per lane may take the one-transcendental pass 2 for waves of
+    # a common whole power; the shapes agree to rounding
+    assert np.allclose(out, base, rtol=2e-6, atol=1e-6 * np.abs(base).max())
     o, scale = ref(inst, idx=np.arange(0, inst.n, 7))
     assert rel_err(out[::7], o, scale).max() <= TOL_F32
 
@@ -319,3 +320,47 @@ def test_clustered_full_size_sampled(ctx, torch):
     for q, x, y, d in zip(on[:40], xs, ys, inst.meta["on_point_data"][:40]):
         if np.count_nonzero((inst.data_x == x) & (inst.data_y == y)) == 1:
             assert out[q] == inst.data_z[d]
+
+
+# ---- standard IDW (constant power) ------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("power", [0.0, 1.0, 2.0, 3.3])
+def test_standard_idw_matches_oracle(ctx, torch, dtype, power):
+    inst = workloads.clustered(m=20000, n=700, seed=31, k=1, dtype=dtype, on_point=0.02)
+    data_xy, data_z, query_xy = aidw.to_device(inst)
+    out = aidw.idw(ctx, data_xy, data_z, query_xy, power).cpu().numpy()
+    want = oracle.idw(inst.data_x, inst.data_y, inst.data_z, inst.query_x, inst.query_y, power)
+    scale = oracle.idw(inst.data_x, inst.data_y, np.abs(inst.data_z), inst.query_x,
+                       inst.query_y, power)
+    assert rel_err(out, want, scale).max() <= (TOL_F64 if dtype == np.float64 else TOL_F32)
+
+
+def test_standard_idw_rejects_negative_power(ctx, torch):
+    d = torch.rand(2, 10, device="cuda")
+    z = torch.rand(10, device="cuda")
+    q = torch.rand(2, 4, device="cuda")
+    with pytest.raises(aidw.AidwError) as ei:
+        aidw.idw(ctx, d, z, q, -1.0)
+    assert ei.value.status == aidw.AIDW_EINVAL
+
+
+# ---- data-access variants (the paper's naive / tiled designs, SoA / AoaS) ----------
+
+@pytest.mark.parametrize("access", [aidw.AIDW_ACCESS_SCALAR, aidw.AIDW_ACCESS_TILED,
+                                    aidw.AIDW_ACCESS_NAIVE])
+@pytest.mark.parametrize("layout", [aidw.AIDW_LAYOUT_SOA, aidw.AIDW_LAYOUT_AOAS])
+@pytest.mark.parametrize("m,n,k", [(1, 3, 1), (255, 257, 8), (5003, 1001, 15)])
+def test_access_variants_match_oracle(ctx, torch, access, layout, m, n, k):
+    inst = workloads.clustered(m=m, n=n, seed=m + n + access, k=k, on_point=0.05)
+    inst.area = max(inst.area, 1e-6) if m > 1 else 1.0
+    data_xy, data_z, query_xy = aidw.to_device(inst)
+    out = torch.full((inst.n,), float("nan"), device="cuda")
+    alpha = torch.empty(inst.n, dtype=torch.float64, device="cuda")
+    ctx.bind_current_stream()
+    p = ctx.problem(data_xy, data_z, query_xy, inst.k, out, inst.levels, inst.R_min, inst.R_max,
+                    inst.area, alpha=alpha)
+    aidw.check(aidw.aidw_interpolate_variant(ctx.h, p, access, layout))
+    (o, _, o_a, _), scale = ref(inst, diag=True)
+    assert rel_err(out.cpu().numpy(), o, scale).max() <= TOL_F32
+    assert np.max(np.abs(alpha.cpu().numpy() - o_a)) <= 1e-5
