@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--m", type=int, default=1 << 20)
     ap.add_argument("--n", type=int, default=1 << 20)
-    ap.add_argument("--cpu-sample", type=int, default=512,
+    ap.add_argument("--cpu-sample", type=int, default=2048,
                     help="queries of the workload timed on the CPU oracle")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true",
@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 512-problem batched launch")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-grid", action="store_true",
+                    help="skip timing pass 1 through the uniform grid (AIDW_FLAG_GRID_KNN)")
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="requests of the Poisson serving run")
     ap.add_argument("--ablation", action="store_true",
@@ -91,8 +93,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(the path shards by queries, see DESIGN.md)" % args.gpus, file=sys.stderr)
+        print("bench.py: runs on one GPU only; --gpus %d is not supported "
+              "(one GPU runs the whole query set; more GPUs would each take a share of the queries)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -193,6 +195,9 @@ def main():
         result["fp64_plain"] = {"ms": ms64, "pair_evals_per_s": pairs / (ms64 * 1e-3),
                                 "speedup_fp32_scaled_vs_fp64": ms64 / ms}
 
+    if not args.no_grid:
+        result["grid_knn"] = bench_grid(ctx, torch, aidw, step_args=(
+            data_xy, data_z, query_xy, inst), full_ms=ms, pairs=pairs)
     if args.ablation:
         result["ablation"] = bench_ablation(ctx, torch, aidw, workloads)
     if not args.no_batch:
@@ -268,6 +273,32 @@ def bench_ablation(ctx, torch, aidw, workloads, sizes=(10240, 51200, 102400, 512
                          "pair_evals_per_s": 2.0 * N * N / (kern * 1e-3)})
     return {"workload": "m = n = N uniform points in [0, 1000]^2, k = 15 (N as in the paper's "
                         "Table 1, 1K = 1024)", "rows": rows}
+
+
+def bench_grid(ctx, torch, aidw, step_args, full_ms, pairs, steps=3):
+    """The same workload with pass 1 through the uniform grid: identical
+    r_obs and alpha, pass 2 still over all m points.  The pair count stays
+    the method's 2 m n, so the rate is an effective one."""
+    data_xy, data_z, query_xy, inst = step_args
+    out = torch.empty(inst.n, dtype=torch.float32, device=data_xy.device)
+    flags = aidw.AIDW_FLAG_ASYNC | aidw.AIDW_FLAG_GRID_KNN
+    print("bench: timing pass 1 through the grid", file=sys.stderr, flush=True)
+
+    def run():
+        ctx.interpolate(data_xy, data_z, query_xy, inst.k, inst.levels, inst.R_min, inst.R_max,
+                        inst.area, flags=flags, out=out)
+
+    run()
+    stream = torch.cuda.current_stream()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    e[0].record(stream)
+    for _ in range(steps):
+        run()
+    e[1].record(stream)
+    torch.cuda.synchronize()
+    ms = e[0].elapsed_time(e[1]) / steps
+    return {"ms_per_step": ms, "effective_pair_evals_per_s": pairs / (ms * 1e-3),
+            "speedup_vs_full_scan": full_ms / ms, "steps": steps}
 
 
 def bench_batched(ctx, torch, aidw, workloads):

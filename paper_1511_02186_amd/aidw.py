@@ -12,7 +12,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libaidw.so")
+# AIDW_LIBRARY selects another build of the library (same ABI), e.g. one made
+# with extra compile options; the in-tree build is the default.
+LIB_PATH = os.environ.get("AIDW_LIBRARY") or os.path.join(HERE, "libaidw.so")
 
 AIDW_OK = 0
 AIDW_EINVAL = -1

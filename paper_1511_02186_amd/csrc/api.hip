@@ -220,10 +220,13 @@ aidw::ProblemF32 problem_f32(const aidw_problem* p) {
 
 namespace {
 
+// Bytes at the start of the handle workspace that hold max |z| of the call.
+constexpr size_t kZmaxSlot = 256;
+
 // Pass 1 through the uniform grid, then pass 2 over all points.
 hipError_t run_grid(aidw_t h, const aidw_problem* p, aidw_status* st_out) {
     const int m = (int)p->m, n = (int)p->n;
-    const aidw::ProblemF32 q = problem_f32(p);
+    aidw::ProblemF32 q = problem_f32(p);
     aidw::GridWorkspace gw{};
     gw.cells = aidw::grid_cells(m);
     gw.nparts = (int)std::min<int64_t>(1024, ((int64_t)m + 255) / 256);
@@ -233,29 +236,32 @@ hipError_t run_grid(aidw_t h, const aidw_problem* p, aidw_status* st_out) {
     const aidw::SplitPlan sp = split_plan_for(h, h->tuning, m, n);
     const size_t a = 256;
     auto up = [&](size_t v) { return (v + a - 1) / a * a; };
-    size_t off[9], bytes = 0;
-    const size_t sizes[9] = {sizeof(aidw::GridGeom), sizeof(float4) * (size_t)gw.nparts,
+    size_t off[10], bytes = 0;
+    const size_t sizes[10] = {kZmaxSlot, sizeof(aidw::GridGeom), sizeof(float4) * (size_t)gw.nparts,
                              sizeof(int) * (cells + 1), sizeof(int) * (cells + 1),
                              sizeof(int) * cells, sizeof(float2) * (size_t)m, gw.temp_bytes,
                              4 * sizeof(float) * (size_t)n,
                              2 * sizeof(double) * (size_t)n * (size_t)sp.segments};
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 0; i < 10; ++i) {
         off[i] = bytes;
         bytes += up(sizes[i]);
     }
     *st_out = ensure_workspace(h, bytes);
     if (*st_out != AIDW_OK) return hipSuccess;
     char* w = static_cast<char*>(h->workspace);
-    gw.geo = reinterpret_cast<aidw::GridGeom*>(w + off[0]);
-    gw.part = reinterpret_cast<float4*>(w + off[1]);
-    gw.counts = reinterpret_cast<int*>(w + off[2]);
-    gw.start = reinterpret_cast<int*>(w + off[3]);
-    gw.cursor = reinterpret_cast<int*>(w + off[4]);
-    gw.sorted = reinterpret_cast<float2*>(w + off[5]);
-    gw.temp = w + off[6];
-    gw.qpar = reinterpret_cast<float*>(w + off[7]);
-    gw.psum = reinterpret_cast<double*>(w + off[8]);
-    hipError_t e = aidw::launch_grid_knn_all(q, gw, h->stream);
+    float* zmax = reinterpret_cast<float*>(w + off[0]);
+    gw.geo = reinterpret_cast<aidw::GridGeom*>(w + off[1]);
+    gw.part = reinterpret_cast<float4*>(w + off[2]);
+    gw.counts = reinterpret_cast<int*>(w + off[3]);
+    gw.start = reinterpret_cast<int*>(w + off[4]);
+    gw.cursor = reinterpret_cast<int*>(w + off[5]);
+    gw.sorted = reinterpret_cast<float2*>(w + off[6]);
+    gw.temp = w + off[7];
+    gw.qpar = reinterpret_cast<float*>(w + off[8]);
+    gw.psum = reinterpret_cast<double*>(w + off[9]);
+    q.zmax = zmax;
+    hipError_t e = aidw::launch_abs_max(q.dz, m, zmax, h->stream);
+    if (e == hipSuccess) e = aidw::launch_grid_knn_all(q, gw, h->stream);
     if (e == hipSuccess) e = aidw::launch_aidw_f32_pass2(q, sp, gw.qpar, gw.psum, h->stream);
     return e;
 }
@@ -276,7 +282,7 @@ aidw_status run_problem(aidw_t h, const aidw_problem* p) {
         e = run_grid(h, p, &gst);
         if (gst != AIDW_OK) return gst;
     } else if (p->precision == AIDW_FP32_SCALED) {
-        const aidw::ProblemF32 q = problem_f32(p);
+        aidw::ProblemF32 q = problem_f32(p);
         aidw_tuning t = h->tuning;
         aidw_tuning tuned;
         if (!t.q_per_lane && !t.max_waves_per_simd && !t.split_segments &&
@@ -287,12 +293,29 @@ aidw_status run_problem(aidw_t h, const aidw_problem* p) {
         aidw::SplitPlan sp{1, m, 0};
         aidw::SplitWorkspace ws{};
         if (!p->knn_idx) sp = split_plan_for(h, t, m, n);
-        if (sp.segments > 1) {
-            aidw_status st = ensure_workspace(h, split_workspace_bytes(sp, p->k, n, nullptr, nullptr));
-            if (st != AIDW_OK) return st;
-            split_workspace_bytes(sp, p->k, n, &ws, static_cast<char*>(h->workspace));
+        // workspace: max |z|, the centred copy of the pass-1 screen (not needed
+        // when kNN indices are tracked), then the split-m buffers
+        const bool screen = !p->knn_idx;
+        const size_t o_prep = kZmaxSlot;
+        const size_t o_split = o_prep + (screen ? (aidw::prep_bytes(m) + 255) / 256 * 256 : 0);
+        const size_t need = o_split + (sp.segments > 1
+                                           ? split_workspace_bytes(sp, p->k, n, nullptr, nullptr)
+                                           : 0);
+        aidw_status st = ensure_workspace(h, need);
+        if (st != AIDW_OK) return st;
+        char* w = static_cast<char*>(h->workspace);
+        if (sp.segments > 1) split_workspace_bytes(sp, p->k, n, &ws, w + o_split);
+        float* zmax = reinterpret_cast<float*>(w);
+        q.zmax = zmax;
+        if (screen) {
+            float* prep = reinterpret_cast<float*>(w + o_prep);
+            q.prep = prep;
+            q.prep_stride = aidw::prep_stride_for(m);
+            e = aidw::launch_prep(q, prep, zmax, h->stream);
+        } else {
+            e = aidw::launch_abs_max(q.dz, m, zmax, h->stream);
         }
-        e = aidw::launch_aidw_f32(q, cfg, &sp, &ws, h->stream);
+        if (e == hipSuccess) e = aidw::launch_aidw_f32(q, cfg, &sp, &ws, h->stream);
     } else {
         const double* xy = static_cast<const double*>(p->data_xy);
         const double* qxy = static_cast<const double*>(p->query_xy);
@@ -496,18 +519,31 @@ aidw_status batch_build(aidw_t h, const aidw_problem* problems, int count, aidw_
                      [&](const aidw::BatchItem& x, const aidw::BatchItem& y) {
                          return probs[x.problem].m > probs[y.problem].m;
                      });
+    // device block: problems | items | counter | max-|z| tasks | max-|z| slots
     const size_t a = 256;
-    const size_t sz_p = (sizeof(aidw::ProblemF32) * probs.size() + a - 1) / a * a;
-    const size_t sz_i = (sizeof(aidw::BatchItem) * items.size() + a - 1) / a * a;
-    const size_t bytes = sz_p + sz_i + a;
+    auto up = [&](size_t v) { return (v + a - 1) / a * a; };
+    const size_t sz_p = up(sizeof(aidw::ProblemF32) * probs.size());
+    const size_t sz_i = up(sizeof(aidw::BatchItem) * items.size());
+    const size_t sz_t = up(sizeof(aidw::AbsMaxTask) * probs.size());
+    const size_t o_t = sz_p + sz_i + a, o_z = o_t + sz_t;
+    const size_t bytes = o_z + up(sizeof(float) * probs.size());
     aidw_status st = device_alloc(h, bytes, &b->device_block);
     if (st != AIDW_OK) return st;
     b->device_bytes = bytes;
     char* base = static_cast<char*>(b->device_block);
+    float* zslots = reinterpret_cast<float*>(base + o_z);
+    std::vector<aidw::AbsMaxTask> tasks(probs.size());
+    for (size_t i = 0; i < probs.size(); ++i) {
+        probs[i].zmax = zslots + i;
+        tasks[i] = aidw::AbsMaxTask{probs[i].dz, zslots + i, probs[i].m};
+    }
     hipError_t e = hipMemcpy(base, probs.data(), sizeof(aidw::ProblemF32) * probs.size(),
                              hipMemcpyHostToDevice);
     if (e == hipSuccess && !items.empty())
         e = hipMemcpy(base + sz_p, items.data(), sizeof(aidw::BatchItem) * items.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !tasks.empty())
+        e = hipMemcpy(base + o_t, tasks.data(), sizeof(aidw::AbsMaxTask) * tasks.size(),
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
     b->h = h;
@@ -515,6 +551,8 @@ aidw_status batch_build(aidw_t h, const aidw_problem* problems, int count, aidw_
     b->launch.problems = reinterpret_cast<const aidw::ProblemF32*>(base);
     b->launch.items = reinterpret_cast<const aidw::BatchItem*>(base + sz_p);
     b->launch.counter = reinterpret_cast<int*>(base + sz_p + sz_i);
+    b->launch.tasks = reinterpret_cast<const aidw::AbsMaxTask*>(base + o_t);
+    b->launch.n_tasks = (int)tasks.size();
     b->launch.n_items = (int)items.size();
     b->launch.K = aidw::k_bucket(kmax);
     int per_cu = aidw::batch_blocks_per_cu(b->launch.K);

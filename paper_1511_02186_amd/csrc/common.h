@@ -36,7 +36,23 @@ struct ProblemF32 {
     int m;
     int n;
     AlphaParams ap;
+    // optional: max |z| over the data (written by launch_abs_max before the
+    // pass-2 kernels); lets whole-power waves skip the d_min rescaling
+    const float* zmax;
+    // optional: centred copy of the data for the screened pass 1 (written by
+    // launch_prep): [kPrepHeader] header, then x', y', |p'|^2, each
+    // prep_stride floats long
+    const float* prep;
+    int prep_stride;
 };
+
+// Header of the prep block: [0] max |p'|^2 (as written by an unsigned
+// atomic max of its bits), [1], [2] the centre subtracted from x and y.
+constexpr int kPrepHeader = 64;
+inline int prep_stride_for(int m) { return (m + 63) / 64 * 64; }
+inline size_t prep_bytes(int m) {
+    return sizeof(float) * ((size_t)kPrepHeader + 3 * (size_t)prep_stride_for(m));
+}
 
 struct ProblemF64 {
     const double* dx;
@@ -92,10 +108,19 @@ struct BatchItem {
 
 // A batched launch: `groups` workgroups of kGroupSize threads whose waves
 // claim items[0..n_items) through `counter` (reset by the launch itself).
+// max |z| of one problem's data into *out (each problem's zmax slot).
+struct AbsMaxTask {
+    const float* z;
+    float* out;
+    int m;
+};
+
 struct BatchLaunch {
     const ProblemF32* problems;  // device array
     const BatchItem* items;      // device array, longest first
     int* counter;                // device int
+    const AbsMaxTask* tasks;     // device array, one per problem (fills problems[i].zmax)
+    int n_tasks;
     int n_items;
     int groups;
     int K;                       // register bucket >= every problem's k
@@ -123,9 +148,11 @@ struct ServeItem {
 };
 
 struct ServeLaunch {
-    const ServeJob* jobs;    // device array
-    const ServeItem* items;  // device array
-    int* counter;            // device int, reset by the launch
+    const ServeJob* jobs;       // device array
+    const ServeItem* items;     // device array
+    int* counter;               // device int, reset by the launch
+    const AbsMaxTask* tasks;    // device array, one per job (fills jobs[i].p.zmax)
+    int n_tasks;
     int n_items;
     int groups;
     int K;
@@ -155,6 +182,14 @@ struct GridWorkspace {
     float* qpar;        // [4][n] as in SplitWorkspace
     double* psum;       // [segments][2][n]
 };
+
+// max |z_i| over m values into *out (one workgroup; NaN wins, inf is kept).
+hipError_t launch_abs_max(const float* z, int m, float* out, hipStream_t s);
+// The same for many arrays, one workgroup per task.
+hipError_t launch_abs_max_tasks(const AbsMaxTask* tasks, int count, hipStream_t s);
+// max |z| into *zmax and the centred data of the pass-1 screen into prep
+// (prep_bytes(m) bytes).
+hipError_t launch_prep(const ProblemF32& p, float* prep, float* zmax, hipStream_t s);
 
 int grid_cells(int64_t m);
 size_t grid_temp_bytes(int cells);

@@ -135,6 +135,78 @@ __device__ __forceinline__ void scan_knn(cptr X, cptr Y, int j0, int j1, const f
     }
 }
 
+// ---- pass 1, screened: every pair first costs three VALU ops -----------------
+// With q' = q - c, p' = p - c for a centre c of the data,
+//   |q - p|^2 = |q'|^2 + (|p'|^2 - 2 q'.p'),
+// and s = fl(fl(-2q'x p'x + fl(-2q'y p'y)) + |p'|^2) takes three operations
+// with one scalar operand each (|p'|^2 is stored with the centred copy).
+// Rounding, cancellation and the centring move s + |q'|^2 away from the
+// FP32 distance d2 that the full scan computes by at most about
+// 6u T + 6u G^2 (u = 2^-24, G = |q'| + max|p'|, T the current k-th
+// distance); the screen threshold T - |q'|^2 + 2^-20 (T + G^2) leaves twice
+// that margin.  So a batch of points whose screen values all reach the
+// threshold holds no point the full scan would insert, and batches that do
+// not are rescanned exactly; the k-nearest list is the full scan's.
+template <int K>
+__device__ __forceinline__ bool scan_knn_screened(const ProblemF32& p, int j0, int j1, float qx,
+                                                  float qy, float (&top)[K]) {
+    const float* hdr = p.prep;
+    const float R = sqrtf(hdr[0]) * (1.0f + 0x1p-20f);  // >= max |p'|
+    const float qcx = qx - hdr[1], qcy = qy - hdr[2];
+    const float Q = fmaf(qcy, qcy, qcx * qcx);
+    const float G = sqrtf(Q) + R;
+    const float G2 = G * G;
+    if (__any(!(G2 < INFINITY))) return false;  // out of range: the caller scans directly
+    const float qx2 = -2.0f * qcx, qy2 = -2.0f * qcy;
+    const cptr CX = as_const(hdr + kPrepHeader);
+    const cptr CY = CX + p.prep_stride;
+    const cptr CP = CY + p.prep_stride;
+    const cptr X = as_const(p.dx), Y = as_const(p.dy);
+    auto threshold = [&]() {
+        const float T = top[K - 1];
+        return (T - Q) + 0x1p-20f * (T + G2);
+    };
+    float thr = threshold();
+    constexpr int B = 16;
+    int j = j0;
+    for (; j + B <= j1; j += B) {
+        float sv[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) sv[u] = fmaf(qx2, CX[j + u], qy2 * CY[j + u]) + CP[j + u];
+        float mn = sv[0];
+#pragma unroll
+        for (int u = 1; u < B; ++u) mn = fminf(mn, sv[u]);
+        if (mn < thr) {
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const float d2 = sqdist(qx, qy, X[j + u], Y[j + u]);
+                if (d2 < top[K - 1]) list_insert<K>(top, d2);
+            }
+            thr = threshold();
+        }
+    }
+    for (; j < j1; ++j) {
+        const float d2 = sqdist(qx, qy, X[j], Y[j]);
+        if (d2 < top[K - 1]) list_insert<K>(top, d2);
+    }
+    return true;
+}
+
+// Pass 1 for one query per lane: screened when the centred copy exists.
+template <int K>
+__device__ __forceinline__ void scan_knn_one(const ProblemF32& p, int j0, int j1, float qx,
+                                             float qy, float (&top)[K]) {
+    if (p.prep && scan_knn_screened<K>(p, j0, j1, qx, qy, top)) return;
+    float qxa[1] = {qx}, qya[1] = {qy};
+    float t[1][K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) t[0][i] = top[i];
+    int tix[1][1];
+    scan_knn<K, 1, false>(as_const(p.dx), as_const(p.dy), j0, j1, qxa, qya, t, tix);
+#pragma unroll
+    for (int i = 0; i < K; ++i) top[i] = t[0][i];
+}
+
 template <int K, int Q, bool TRACK>
 __device__ __forceinline__ void init_lists(float (&top)[Q][K],
                                            int (&tix)[TRACK ? Q : 1][TRACK ? K : 1], int k) {
@@ -212,11 +284,20 @@ __device__ __forceinline__ float ipow(float s) {
 
 // Pass 2 for a wave whose queries all have the same integer power A and a
 // normal, nonzero d_min: w = (d_min / d)^A = (d_min * rsq(d^2))^A, one
-// transcendental instead of two.
-template <int A>
+// transcendental instead of two.  Without SCALED the common factor d_min^-A
+// is left in (w = rsq(d^2)^A, one multiply less per pair); the caller allows
+// that only where every weight and every w*z stays inside the FP32 range.
+template <int A, bool SCALED>
 __device__ __forceinline__ void scan_wsum_int(cptr X, cptr Y, cptr Z, int j0, int j1, float qx,
                                               float qy, float dmin, double& Sw, double& Swz) {
+    // No fusing of w's last product into sw += w: Σw and Σwz then round
+    // alike (a constant field comes out exact).  The explicit fmaf calls stay.
+#pragma clang fp contract(off)
     constexpr int B = batch2_for<1>();
+    auto weight = [&](float d2) {
+        const float r = __builtin_amdgcn_rsqf(d2);
+        return ipow<A>(SCALED ? dmin * r : r);
+    };
     int j = j0;
     for (; j + B <= j1; j += B) {
         float px[B], py[B], pz[B];
@@ -226,10 +307,11 @@ __device__ __forceinline__ void scan_wsum_int(cptr X, cptr Y, cptr Z, int j0, in
             py[u] = Y[j + u];
             pz[u] = Z[j + u];
         }
-        float sw = 0.0f, swz = 0.0f;
+        float w0 = weight(sqdist(qx, qy, px[0], py[0]));
+        float sw = w0, swz = w0 * pz[0];
 #pragma unroll
-        for (int u = 0; u < B; ++u) {
-            const float w = ipow<A>(dmin * __builtin_amdgcn_rsqf(sqdist(qx, qy, px[u], py[u])));
+        for (int u = 1; u < B; ++u) {
+            const float w = weight(sqdist(qx, qy, px[u], py[u]));
             sw += w;
             swz = fmaf(w, pz[u], swz);
         }
@@ -237,10 +319,31 @@ __device__ __forceinline__ void scan_wsum_int(cptr X, cptr Y, cptr Z, int j0, in
         Swz += (double)swz;
     }
     for (; j < j1; ++j) {
-        const float w = ipow<A>(dmin * __builtin_amdgcn_rsqf(sqdist(qx, qy, X[j], Y[j])));
+        const float w = weight(sqdist(qx, qy, X[j], Y[j]));
         Sw += (double)w;
         Swz += (double)(w * Z[j]);
     }
+}
+
+// True when the weights rsq(d^2)^A = d^-A of a query can be summed unscaled:
+// L = A log2(d_min) (= aL0) bounds every weight by 2^-L.  Needs L <= 60 (the
+// nearest weight stays >= 2^-60, so far weights lost to underflow are
+// negligible) and 16 * 2^-L * max|z| < 2^124 (no FP32 batch sum overflows).
+__device__ __forceinline__ bool unscaled_ok(float aL0, const float* zmax) {
+    if (!zmax) return false;
+    const float zm = *zmax;
+    const float lim = fminf(100.0f, 120.0f - __builtin_amdgcn_logf(zm));  // inf when zm = 0
+    return aL0 <= 60.0f && -aL0 <= lim;
+}
+
+template <int A>
+__device__ __forceinline__ void scan_wsum_int_any(cptr X, cptr Y, cptr Z, int j0, int j1,
+                                                  float qx, float qy, float dmin, bool unscaled,
+                                                  double& Sw, double& Swz) {
+    if (__all(unscaled))
+        scan_wsum_int<A, false>(X, Y, Z, j0, j1, qx, qy, dmin, Sw, Swz);
+    else
+        scan_wsum_int<A, true>(X, Y, Z, j0, j1, qx, qy, dmin, Sw, Swz);
 }
 
 // Pass 2 for one lane's queries: the whole-power loop when every lane of the
@@ -250,20 +353,19 @@ __device__ __forceinline__ void scan_wsum_any(cptr X, cptr Y, cptr Z, int j0, in
                                               const float (&qx)[Q], const float (&qy)[Q],
                                               const float (&na)[Q], const float (&aL0)[Q],
                                               double (&Sw)[Q], double (&Swz)[Q],
-                                              int ipw = 0, float dmin = 0.0f) {
+                                              int ipw = 0, float dmin = 0.0f,
+                                              const float* zmax = nullptr) {
     if constexpr (Q == 1) {
         // same whole power in every lane: the one-transcendental loop
         const int a0 = __builtin_amdgcn_readfirstlane(ipw);
         if (a0 != 0 && __all(ipw == a0)) {
+            const bool un = unscaled_ok(aL0[0], zmax);
             switch (a0) {
-                case 1: return scan_wsum_int<1>(X, Y, Z, j0, j1, qx[0], qy[0], dmin, Sw[0], Swz[0]);
-                case 2: return scan_wsum_int<2>(X, Y, Z, j0, j1, qx[0], qy[0], dmin, Sw[0], Swz[0]);
-                case 3: return scan_wsum_int<3>(X, Y, Z, j0, j1, qx[0], qy[0], dmin, Sw[0], Swz[0]);
-                case 4: return scan_wsum_int<4>(X, Y, Z, j0, j1, qx[0], qy[0], dmin, Sw[0], Swz[0]);
-                case 5: return scan_wsum_int<5>(X, Y, Z, j0, j1, qx[0], qy[0], dmin, Sw[0], Swz[0]);
-                case 6: return scan_wsum_int<6>(X, Y, Z, j0, j1, qx[0], qy[0], dmin, Sw[0], Swz[0]);
-                case 7: return scan_wsum_int<7>(X, Y, Z, j0, j1, qx[0], qy[0], dmin, Sw[0], Swz[0]);
-                case 8: return scan_wsum_int<8>(X, Y, Z, j0, j1, qx[0], qy[0], dmin, Sw[0], Swz[0]);
+#define AIDW_INT_CASE(A) \
+    case A: return scan_wsum_int_any<A>(X, Y, Z, j0, j1, qx[0], qy[0], dmin, un, Sw[0], Swz[0]);
+                AIDW_INT_CASE(1) AIDW_INT_CASE(2) AIDW_INT_CASE(3) AIDW_INT_CASE(4)
+                AIDW_INT_CASE(5) AIDW_INT_CASE(6) AIDW_INT_CASE(7) AIDW_INT_CASE(8)
+#undef AIDW_INT_CASE
                 default: break;
             }
         }
@@ -300,7 +402,10 @@ __device__ __forceinline__ void fused_tile(const ProblemF32& p, int base) {
     float top[Q][K];
     int tix[TRACK ? Q : 1][TRACK ? K : 1];
     init_lists<K, Q, TRACK>(top, tix, p.ap.k);
-    scan_knn<K, Q, TRACK>(as_const(p.dx), as_const(p.dy), 0, p.m, qx, qy, top, tix);
+    if constexpr (Q == 1 && !TRACK)
+        scan_knn_one<K>(p, 0, p.m, qx[0], qy[0], top[0]);
+    else
+        scan_knn<K, Q, TRACK>(as_const(p.dx), as_const(p.dy), 0, p.m, qx, qy, top, tix);
 
     const int pad = K - p.ap.k;
     float na[Q], aL0[Q], d2min[Q];
@@ -325,7 +430,7 @@ __device__ __forceinline__ void fused_tile(const ProblemF32& p, int base) {
 #pragma unroll
     for (int s = 0; s < Q; ++s) Sw[s] = Swz[s] = 0.0;
     scan_wsum_any<Q>(as_const(p.dx), as_const(p.dy), as_const(p.dz), 0, p.m, qx, qy, na, aL0, Sw,
-                     Swz, ipw, sqrtf(d2min[0]));
+                     Swz, ipw, sqrtf(d2min[0]), p.zmax);
 
 #pragma unroll
     for (int s = 0; s < Q; ++s)
@@ -414,7 +519,7 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_knn_part(ProblemF32 p, Sp
     float top[1][K];
     int tix[1][1];
     init_lists<K, 1, false>(top, tix, p.ap.k);
-    scan_knn<K, 1, false>(as_const(p.dx), as_const(p.dy), j0, j1, qx, qy, top, tix);
+    scan_knn_one<K>(p, j0, j1, qx[0], qy[0], top[0]);
     store_partial<K>(top[0], p, seg, qi[0], part);
 }
 
@@ -445,7 +550,7 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_wsum_part(ProblemF32 p, S
     float na[1] = {qpar[c]}, aL0[1] = {qpar[p.n + c]};
     double Sw[1] = {0.0}, Swz[1] = {0.0};
     scan_wsum_any<1>(as_const(p.dx), as_const(p.dy), as_const(p.dz), j0, j1, qx, qy, na, aL0, Sw,
-                     Swz, (int)qpar[3 * p.n + c], qpar[2 * p.n + c]);
+                     Swz, (int)qpar[3 * p.n + c], qpar[2 * p.n + c], p.zmax);
     if (qi[0] < p.n) {
         psum[((int64_t)seg * 2 + 0) * p.n + qi[0]] = Sw[0];
         psum[((int64_t)seg * 2 + 1) * p.n + qi[0]] = Swz[0];
@@ -464,6 +569,102 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_wsum_reduce(ProblemF32 p,
     p.out[q] = (float)(Swz / Sw);
 }
 
+
+// max |z| as the largest bit pattern of |z| (ordered like the values for
+// non-negative floats; NaN patterns sort above infinity).
+template <int T>
+__device__ __forceinline__ void abs_max_block(const float* __restrict__ z, int m,
+                                              float* __restrict__ out) {
+    __shared__ unsigned s[T];
+    unsigned v = 0;
+    for (int i = threadIdx.x; i < m; i += T) v = max(v, __float_as_uint(z[i]) & 0x7fffffffu);
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = T / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = __uint_as_float(s[0]);
+}
+
+__global__ __launch_bounds__(1024) void aidw_abs_max(const float* __restrict__ z, int m,
+                                                     float* __restrict__ out) {
+    abs_max_block<1024>(z, m, out);
+}
+
+// Statistics for the prep block (one workgroup): bounding-box centre into
+// hdr[1], hdr[2], max |z| into *zmax, and hdr[0] cleared for launch_prep's
+// atomic maximum.
+__global__ __launch_bounds__(1024) void aidw_prep_stats(ProblemF32 p, float* __restrict__ hdr,
+                                                        float* __restrict__ zmax) {
+    __shared__ float s[4][1024];
+    __shared__ unsigned zs[1024];
+    float x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY;
+    unsigned zb = 0;
+    for (int i = threadIdx.x; i < p.m; i += 1024) {
+        const float x = p.dx[i], y = p.dy[i];
+        x0 = fminf(x0, x);
+        x1 = fmaxf(x1, x);
+        y0 = fminf(y0, y);
+        y1 = fmaxf(y1, y);
+        zb = max(zb, __float_as_uint(p.dz[i]) & 0x7fffffffu);
+    }
+    s[0][threadIdx.x] = x0;
+    s[1][threadIdx.x] = y0;
+    s[2][threadIdx.x] = x1;
+    s[3][threadIdx.x] = y1;
+    zs[threadIdx.x] = zb;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        const int t = threadIdx.x;
+        if (t < w) {
+            s[0][t] = fminf(s[0][t], s[0][t + w]);
+            s[1][t] = fminf(s[1][t], s[1][t + w]);
+            s[2][t] = fmaxf(s[2][t], s[2][t + w]);
+            s[3][t] = fmaxf(s[3][t], s[3][t + w]);
+            zs[t] = max(zs[t], zs[t + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        hdr[0] = 0.0f;
+        hdr[1] = s[0][0] + 0.5f * (s[2][0] - s[0][0]);
+        hdr[2] = s[1][0] + 0.5f * (s[3][0] - s[1][0]);
+        zmax[0] = __uint_as_float(zs[0]);
+    }
+}
+
+// Centred copy x' = x - c_x, y' = y - c_y, |p'|^2 = fma(y', y', x' x'), and
+// the maximum of |p'|^2 into hdr[0] (bit patterns of non-negative floats
+// order like their values; NaN and inf disable the screen).
+__global__ __launch_bounds__(256) void aidw_prep_centre(ProblemF32 p, float* __restrict__ prep) {
+    __shared__ unsigned s[256];
+    const float cx = prep[1], cy = prep[2];
+    float* X = prep + kPrepHeader;
+    float* Y = X + p.prep_stride;
+    float* P = Y + p.prep_stride;
+    unsigned v = 0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < p.m; i += gridDim.x * 256) {
+        const float x = p.dx[i] - cx, y = p.dy[i] - cy;
+        const float pp = fmaf(y, y, x * x);
+        X[i] = x;
+        Y[i] = y;
+        P[i] = pp;
+        v = max(v, __float_as_uint(pp) & 0x7fffffffu);
+    }
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(reinterpret_cast<unsigned*>(prep), s[0]);
+}
+
+__global__ __launch_bounds__(256) void aidw_abs_max_tasks(const AbsMaxTask* __restrict__ tasks) {
+    const AbsMaxTask t = tasks[blockIdx.x];
+    abs_max_block<256>(t.z, t.m, t.out);
+}
 
 // ---- serving: fused tiles and split segments in one launch -----------------
 // Pass-1 segment items write their partial lists; the last segment of a tile
@@ -509,7 +710,7 @@ __device__ __forceinline__ void serve_item(const ServeJob& J, const ServeItem& i
     float na[1] = {J.ws.qpar[c]}, aL0[1] = {J.ws.qpar[p.n + c]};
     double Sw[1] = {0.0}, Swz[1] = {0.0};
     scan_wsum_any<1>(as_const(p.dx), as_const(p.dy), as_const(p.dz), j0, j1, qx, qy, na, aL0, Sw,
-                     Swz, (int)J.ws.qpar[3 * p.n + c], J.ws.qpar[2 * p.n + c]);
+                     Swz, (int)J.ws.qpar[3 * p.n + c], J.ws.qpar[2 * p.n + c], p.zmax);
     if (qi[0] < p.n) {
         J.ws.psum[((int64_t)it.seg * 2 + 0) * p.n + qi[0]] = Sw[0];
         J.ws.psum[((int64_t)it.seg * 2 + 1) * p.n + qi[0]] = Swz[0];
@@ -600,6 +801,9 @@ hipError_t launch_single_k(const ProblemF32& p, const LaunchF32& cfg, const Spli
 template <int K>
 hipError_t launch_batch_k(const BatchLaunch& b, hipStream_t stream) {
     hipLaunchKernelGGL(aidw_reset_counter, dim3(1), dim3(64), 0, stream, b.counter);
+    if (b.n_tasks > 0)
+        hipLaunchKernelGGL(aidw_abs_max_tasks, dim3((unsigned)b.n_tasks), dim3(256), 0, stream,
+                           b.tasks);
     hipLaunchKernelGGL((aidw_f32_batch<K>), dim3(b.groups), dim3(kGroupSize), 0, stream,
                        b.problems, b.items, b.n_items, b.counter);
     return hipGetLastError();
@@ -617,6 +821,9 @@ int batch_occupancy_k() {
 template <int K>
 hipError_t launch_serve_k(const ServeLaunch& sl, hipStream_t stream) {
     hipLaunchKernelGGL(aidw_reset_counter, dim3(1), dim3(64), 0, stream, sl.counter);
+    if (sl.n_tasks > 0)
+        hipLaunchKernelGGL(aidw_abs_max_tasks, dim3((unsigned)sl.n_tasks), dim3(256), 0, stream,
+                           sl.tasks);
     hipLaunchKernelGGL((aidw_f32_serve<K>), dim3(sl.groups), dim3(kGroupSize), 0, stream, sl.jobs,
                        sl.items, sl.n_items, sl.counter);
     return hipGetLastError();
@@ -653,6 +860,26 @@ hipError_t launch_aidw_f32(const ProblemF32& p, const LaunchF32& cfg, const Spli
     AIDW_K_DISPATCH(k_bucket(p.ap.k), CALL)
 #undef CALL
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_abs_max(const float* z, int m, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(aidw_abs_max, dim3(1), dim3(1024), 0, s, z, m, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep(const ProblemF32& p, float* prep, float* zmax, hipStream_t s) {
+    ProblemF32 q = p;
+    q.prep_stride = prep_stride_for(p.m);
+    hipLaunchKernelGGL(aidw_prep_stats, dim3(1), dim3(1024), 0, s, q, prep, zmax);
+    const unsigned blocks = (unsigned)std::min<int64_t>(2048, ((int64_t)p.m + 255) / 256);
+    hipLaunchKernelGGL(aidw_prep_centre, dim3(blocks), dim3(256), 0, s, q, prep);
+    return hipGetLastError();
+}
+
+hipError_t launch_abs_max_tasks(const AbsMaxTask* tasks, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(aidw_abs_max_tasks, dim3((unsigned)count), dim3(256), 0, s, tasks);
+    return hipGetLastError();
 }
 
 hipError_t launch_aidw_f32_pass2(const ProblemF32& p, SplitPlan sp, const float* qpar,

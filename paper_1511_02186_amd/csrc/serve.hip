@@ -94,15 +94,29 @@ class HipExecutor : public sv::Executor {
             const sv::Item& it = plan.items[i];
             items[i] = aidw::ServeItem{index[it.ticket], it.phase, it.tile, it.seg};
         }
+        // staging: jobs | items | counter | max-|z| tasks | max-|z| slots (one per job,
+        // recomputed by every tick that carries the job, on the tick's own stream)
         const size_t b_jobs = align_up(sizeof(aidw::ServeJob) * sj.size());
         const size_t b_items = align_up(sizeof(aidw::ServeItem) * items.size());
-        const size_t bytes = b_jobs + b_items + kAlign;
+        const size_t b_tasks = align_up(sizeof(aidw::AbsMaxTask) * sj.size());
+        const size_t o_tasks = b_jobs + b_items + kAlign, o_z = o_tasks + b_tasks;
+        const size_t bytes = o_z + align_up(sizeof(float) * sj.size());
         if (grow(s, bytes) != AIDW_OK) return AIDW_ENOMEM;
         char* host = static_cast<char*>(s.host);
+        char* dev = static_cast<char*>(s.dev);
+        float* zslots = reinterpret_cast<float*>(dev + o_z);
+        std::vector<aidw::AbsMaxTask> tasks(sj.size());
+        for (size_t i = 0; i < sj.size(); ++i) {
+            sj[i].p.zmax = zslots + i;
+            tasks[i] = aidw::AbsMaxTask{sj[i].p.dz, zslots + i, sj[i].p.m};
+        }
         memcpy(host, sj.data(), sizeof(aidw::ServeJob) * sj.size());
         memcpy(host + b_jobs, items.data(), sizeof(aidw::ServeItem) * items.size());
-        char* dev = static_cast<char*>(s.dev);
+        memcpy(host + o_tasks, tasks.data(), sizeof(aidw::AbsMaxTask) * tasks.size());
         hipError_t e = hipMemcpyAsync(dev, host, b_jobs + b_items, hipMemcpyHostToDevice, s.stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dev + o_tasks, host + o_tasks, sizeof(aidw::AbsMaxTask) * tasks.size(),
+                               hipMemcpyHostToDevice, s.stream);
         // arrival counters start at zero before a split job's first item
         for (uint64_t t : plan.jobs) {
             JobRec& r = jobs[t];
@@ -115,10 +129,12 @@ class HipExecutor : public sv::Executor {
             error = hip_fail(e, "tick upload");
             return AIDW_EDEVICE;
         }
-        aidw::ServeLaunch sl;
+        aidw::ServeLaunch sl{};
         sl.jobs = reinterpret_cast<const aidw::ServeJob*>(dev);
         sl.items = reinterpret_cast<const aidw::ServeItem*>(dev + b_jobs);
         sl.counter = reinterpret_cast<int*>(dev + b_jobs + b_items);
+        sl.tasks = reinterpret_cast<const aidw::AbsMaxTask*>(dev + o_tasks);
+        sl.n_tasks = (int)tasks.size();
         sl.n_items = (int)items.size();
         sl.K = aidw::k_bucket(K);
         if (!blocks_per_cu[sl.K]) blocks_per_cu[sl.K] = std::max(1, aidw::serve_blocks_per_cu(sl.K));

@@ -364,3 +364,82 @@ def test_access_variants_match_oracle(ctx, torch, access, layout, m, n, k):
     (o, _, o_a, _), scale = ref(inst, diag=True)
     assert rel_err(out.cpu().numpy(), o, scale).max() <= TOL_F32
     assert np.max(np.abs(alpha.cpu().numpy() - o_a)) <= 1e-5
+
+
+# ---- whole powers: the unscaled weights only where FP32 holds them -----------------
+
+@pytest.mark.parametrize("coord_scale", [1e-7, 1.0, 1e3, 1e7])
+@pytest.mark.parametrize("z_scale", [1.0, 1e30])
+@pytest.mark.parametrize("power", [1.0, 2.0, 5.0, 8.0])
+def test_whole_power_weights_in_range(ctx, torch, coord_scale, z_scale, power):
+    # every level equal: alpha is the whole number `power` for every query, so
+    # every wave takes the one-transcendental path; the range of d^-power and of
+    # max|z| decides whether the d_min rescaling may be skipped
+    inst = workloads.clustered(m=6000, n=900, seed=int(power) + 3, k=8, on_point=0.0)
+    inst.data_x = (inst.data_x * coord_scale).astype(np.float32)
+    inst.data_y = (inst.data_y * coord_scale).astype(np.float32)
+    inst.query_x = (inst.query_x * coord_scale).astype(np.float32)
+    inst.query_y = (inst.query_y * coord_scale).astype(np.float32)
+    inst.data_z = (inst.data_z * z_scale).astype(np.float32)
+    inst.area = workloads.bbox_area(inst.data_x, inst.data_y)
+    inst.levels = (power,) * 5
+    out = gpu_run(ctx, torch, inst)
+    assert np.all(np.isfinite(out))
+    o, scale = ref(inst)
+    err = rel_err(out, o, scale)
+    say("power %g coords x%g z x%g: max err %.3e" % (power, coord_scale, z_scale, err.max()))
+    assert err.max() <= TOL_F32
+
+
+# ---- the screened pass 1 keeps exactly the full scan's k nearest ---------------------
+
+def _r_obs_alpha(ctx, torch, inst, track):
+    data_xy, data_z, query_xy = aidw.to_device(inst)
+    n = inst.n
+    out = torch.empty(n, device="cuda")
+    r = torch.empty(n, dtype=torch.float64, device="cuda")
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    knn = torch.empty((n, inst.k), dtype=torch.int32, device="cuda") if track else None
+    ctx.bind_current_stream()
+    p = ctx.problem(data_xy, data_z, query_xy, inst.k, out, inst.levels, inst.R_min, inst.R_max,
+                    inst.area, r_obs=r, alpha=a, knn_idx=knn)
+    aidw.check(aidw.aidw_interpolate_ex(ctx.h, p))
+    torch.cuda.synchronize()
+    return r.cpu().numpy(), a.cpu().numpy(), out.cpu().numpy()
+
+
+@pytest.mark.parametrize("case", ["offset", "tiny", "clustered", "duplicates", "line"])
+@pytest.mark.parametrize("k", [1, 7, 32])
+def test_screened_pass1_equals_direct_scan(ctx, torch, case, k):
+    # kNN-index tracking forces the direct scan; without it pass 1 is screened
+    rng = np.random.default_rng(k * 31 + len(case))
+    m, n = 9000, 1500
+    if case == "offset":  # large coordinates, small spread: strong cancellation
+        dx, dy = 1e5 + rng.random(m), -3e4 + rng.random(m)
+    elif case == "tiny":
+        dx, dy = 1e-6 * rng.random(m), 1e-6 * rng.random(m)
+    elif case == "clustered":
+        c = rng.random((8, 2))
+        pick = rng.integers(0, 8, m)
+        dx = c[pick, 0] + 1e-4 * rng.standard_normal(m)
+        dy = c[pick, 1] + 1e-4 * rng.standard_normal(m)
+    elif case == "duplicates":
+        bx, by = rng.random(m // 3), rng.random(m // 3)
+        dx, dy = np.tile(bx, 3), np.tile(by, 3)
+    else:  # all on one line
+        dx, dy = rng.random(m), np.full(m, 0.5)
+    lo_x, hi_x, lo_y, hi_y = dx.min(), dx.max(), dy.min(), dy.max()
+    qx = rng.uniform(lo_x - 0.1 * (hi_x - lo_x), hi_x + 0.1 * (hi_x - lo_x), n)
+    qy = rng.uniform(lo_y - 0.1 * (hi_y - lo_y) - 1e-7, hi_y + 0.1 * (hi_y - lo_y) + 1e-7, n)
+    qx[:50], qy[:50] = dx[:50], dy[:50]  # on-point queries
+    inst = workloads.uniform_unit(m=m, n=n, k=k, seed=1, dtype=np.float32)
+    inst.data_x, inst.data_y = dx.astype(np.float32), dy.astype(np.float32)
+    inst.query_x, inst.query_y = qx.astype(np.float32), qy.astype(np.float32)
+    inst.data_z = rng.standard_normal(m).astype(np.float32)
+    inst.area = max(workloads.bbox_area(inst.data_x, inst.data_y), 1e-12)
+    r0, a0, o0 = _r_obs_alpha(ctx, torch, inst, track=True)
+    r1, a1, o1 = _r_obs_alpha(ctx, torch, inst, track=False)
+    assert np.array_equal(r0, r1)
+    assert np.array_equal(a0, a1)
+    # the untracked run may split m into segments: same sums up to FP64 order
+    assert np.allclose(o1, o0, rtol=1e-6, atol=1e-30)
