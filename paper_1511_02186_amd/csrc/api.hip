@@ -293,28 +293,17 @@ aidw_status run_problem(aidw_t h, const aidw_problem* p) {
         aidw::SplitPlan sp{1, m, 0};
         aidw::SplitWorkspace ws{};
         if (!p->knn_idx) sp = split_plan_for(h, t, m, n);
-        // workspace: max |z|, the centred copy of the pass-1 screen (not needed
-        // when kNN indices are tracked), then the split-m buffers
-        const bool screen = !p->knn_idx;
-        const size_t o_prep = kZmaxSlot;
-        const size_t o_split = o_prep + (screen ? (aidw::prep_bytes(m) + 255) / 256 * 256 : 0);
-        const size_t need = o_split + (sp.segments > 1
-                                           ? split_workspace_bytes(sp, p->k, n, nullptr, nullptr)
-                                           : 0);
+        // workspace: max |z| in the first slot, then the split-m buffers
+        const size_t need = kZmaxSlot + (sp.segments > 1
+                                             ? split_workspace_bytes(sp, p->k, n, nullptr, nullptr)
+                                             : 0);
         aidw_status st = ensure_workspace(h, need);
         if (st != AIDW_OK) return st;
         char* w = static_cast<char*>(h->workspace);
-        if (sp.segments > 1) split_workspace_bytes(sp, p->k, n, &ws, w + o_split);
+        if (sp.segments > 1) split_workspace_bytes(sp, p->k, n, &ws, w + kZmaxSlot);
         float* zmax = reinterpret_cast<float*>(w);
         q.zmax = zmax;
-        if (screen) {
-            float* prep = reinterpret_cast<float*>(w + o_prep);
-            q.prep = prep;
-            q.prep_stride = aidw::prep_stride_for(m);
-            e = aidw::launch_prep(q, prep, zmax, h->stream);
-        } else {
-            e = aidw::launch_abs_max(q.dz, m, zmax, h->stream);
-        }
+        e = aidw::launch_abs_max(q.dz, m, zmax, h->stream);
         if (e == hipSuccess) e = aidw::launch_aidw_f32(q, cfg, &sp, &ws, h->stream);
     } else {
         const double* xy = static_cast<const double*>(p->data_xy);

@@ -39,20 +39,7 @@ struct ProblemF32 {
     // optional: max |z| over the data (written by launch_abs_max before the
     // pass-2 kernels); lets whole-power waves skip the d_min rescaling
     const float* zmax;
-    // optional: centred copy of the data for the screened pass 1 (written by
-    // launch_prep): [kPrepHeader] header, then x', y', |p'|^2, each
-    // prep_stride floats long
-    const float* prep;
-    int prep_stride;
 };
-
-// Header of the prep block: [0] max |p'|^2 (as written by an unsigned
-// atomic max of its bits), [1], [2] the centre subtracted from x and y.
-constexpr int kPrepHeader = 64;
-inline int prep_stride_for(int m) { return (m + 63) / 64 * 64; }
-inline size_t prep_bytes(int m) {
-    return sizeof(float) * ((size_t)kPrepHeader + 3 * (size_t)prep_stride_for(m));
-}
 
 struct ProblemF64 {
     const double* dx;
@@ -187,9 +174,6 @@ struct GridWorkspace {
 hipError_t launch_abs_max(const float* z, int m, float* out, hipStream_t s);
 // The same for many arrays, one workgroup per task.
 hipError_t launch_abs_max_tasks(const AbsMaxTask* tasks, int count, hipStream_t s);
-// max |z| into *zmax and the centred data of the pass-1 screen into prep
-// (prep_bytes(m) bytes).
-hipError_t launch_prep(const ProblemF32& p, float* prep, float* zmax, hipStream_t s);
 
 int grid_cells(int64_t m);
 size_t grid_temp_bytes(int cells);

@@ -135,78 +135,6 @@ __device__ __forceinline__ void scan_knn(cptr X, cptr Y, int j0, int j1, const f
     }
 }
 
-// ---- pass 1, screened: every pair first costs three VALU ops -----------------
-// With q' = q - c, p' = p - c for a centre c of the data,
-//   |q - p|^2 = |q'|^2 + (|p'|^2 - 2 q'.p'),
-// and s = fl(fl(-2q'x p'x + fl(-2q'y p'y)) + |p'|^2) takes three operations
-// with one scalar operand each (|p'|^2 is stored with the centred copy).
-// Rounding, cancellation and the centring move s + |q'|^2 away from the
-// FP32 distance d2 that the full scan computes by at most about
-// 6u T + 6u G^2 (u = 2^-24, G = |q'| + max|p'|, T the current k-th
-// distance); the screen threshold T - |q'|^2 + 2^-20 (T + G^2) leaves twice
-// that margin.  So a batch of points whose screen values all reach the
-// threshold holds no point the full scan would insert, and batches that do
-// not are rescanned exactly; the k-nearest list is the full scan's.
-template <int K>
-__device__ __forceinline__ bool scan_knn_screened(const ProblemF32& p, int j0, int j1, float qx,
-                                                  float qy, float (&top)[K]) {
-    const float* hdr = p.prep;
-    const float R = sqrtf(hdr[0]) * (1.0f + 0x1p-20f);  // >= max |p'|
-    const float qcx = qx - hdr[1], qcy = qy - hdr[2];
-    const float Q = fmaf(qcy, qcy, qcx * qcx);
-    const float G = sqrtf(Q) + R;
-    const float G2 = G * G;
-    if (__any(!(G2 < INFINITY))) return false;  // out of range: the caller scans directly
-    const float qx2 = -2.0f * qcx, qy2 = -2.0f * qcy;
-    const cptr CX = as_const(hdr + kPrepHeader);
-    const cptr CY = CX + p.prep_stride;
-    const cptr CP = CY + p.prep_stride;
-    const cptr X = as_const(p.dx), Y = as_const(p.dy);
-    auto threshold = [&]() {
-        const float T = top[K - 1];
-        return (T - Q) + 0x1p-20f * (T + G2);
-    };
-    float thr = threshold();
-    constexpr int B = 16;
-    int j = j0;
-    for (; j + B <= j1; j += B) {
-        float sv[B];
-#pragma unroll
-        for (int u = 0; u < B; ++u) sv[u] = fmaf(qx2, CX[j + u], qy2 * CY[j + u]) + CP[j + u];
-        float mn = sv[0];
-#pragma unroll
-        for (int u = 1; u < B; ++u) mn = fminf(mn, sv[u]);
-        if (mn < thr) {
-#pragma unroll
-            for (int u = 0; u < B; ++u) {
-                const float d2 = sqdist(qx, qy, X[j + u], Y[j + u]);
-                if (d2 < top[K - 1]) list_insert<K>(top, d2);
-            }
-            thr = threshold();
-        }
-    }
-    for (; j < j1; ++j) {
-        const float d2 = sqdist(qx, qy, X[j], Y[j]);
-        if (d2 < top[K - 1]) list_insert<K>(top, d2);
-    }
-    return true;
-}
-
-// Pass 1 for one query per lane: screened when the centred copy exists.
-template <int K>
-__device__ __forceinline__ void scan_knn_one(const ProblemF32& p, int j0, int j1, float qx,
-                                             float qy, float (&top)[K]) {
-    if (p.prep && scan_knn_screened<K>(p, j0, j1, qx, qy, top)) return;
-    float qxa[1] = {qx}, qya[1] = {qy};
-    float t[1][K];
-#pragma unroll
-    for (int i = 0; i < K; ++i) t[0][i] = top[i];
-    int tix[1][1];
-    scan_knn<K, 1, false>(as_const(p.dx), as_const(p.dy), j0, j1, qxa, qya, t, tix);
-#pragma unroll
-    for (int i = 0; i < K; ++i) top[i] = t[0][i];
-}
-
 template <int K, int Q, bool TRACK>
 __device__ __forceinline__ void init_lists(float (&top)[Q][K],
                                            int (&tix)[TRACK ? Q : 1][TRACK ? K : 1], int k) {
@@ -402,10 +330,7 @@ __device__ __forceinline__ void fused_tile(const ProblemF32& p, int base) {
     float top[Q][K];
     int tix[TRACK ? Q : 1][TRACK ? K : 1];
     init_lists<K, Q, TRACK>(top, tix, p.ap.k);
-    if constexpr (Q == 1 && !TRACK)
-        scan_knn_one<K>(p, 0, p.m, qx[0], qy[0], top[0]);
-    else
-        scan_knn<K, Q, TRACK>(as_const(p.dx), as_const(p.dy), 0, p.m, qx, qy, top, tix);
+    scan_knn<K, Q, TRACK>(as_const(p.dx), as_const(p.dy), 0, p.m, qx, qy, top, tix);
 
     const int pad = K - p.ap.k;
     float na[Q], aL0[Q], d2min[Q];
@@ -519,7 +444,7 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_knn_part(ProblemF32 p, Sp
     float top[1][K];
     int tix[1][1];
     init_lists<K, 1, false>(top, tix, p.ap.k);
-    scan_knn_one<K>(p, j0, j1, qx[0], qy[0], top[0]);
+    scan_knn<K, 1, false>(as_const(p.dx), as_const(p.dy), j0, j1, qx, qy, top, tix);
     store_partial<K>(top[0], p, seg, qi[0], part);
 }
 
@@ -590,75 +515,6 @@ __device__ __forceinline__ void abs_max_block(const float* __restrict__ z, int m
 __global__ __launch_bounds__(1024) void aidw_abs_max(const float* __restrict__ z, int m,
                                                      float* __restrict__ out) {
     abs_max_block<1024>(z, m, out);
-}
-
-// Statistics for the prep block (one workgroup): bounding-box centre into
-// hdr[1], hdr[2], max |z| into *zmax, and hdr[0] cleared for launch_prep's
-// atomic maximum.
-__global__ __launch_bounds__(1024) void aidw_prep_stats(ProblemF32 p, float* __restrict__ hdr,
-                                                        float* __restrict__ zmax) {
-    __shared__ float s[4][1024];
-    __shared__ unsigned zs[1024];
-    float x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY;
-    unsigned zb = 0;
-    for (int i = threadIdx.x; i < p.m; i += 1024) {
-        const float x = p.dx[i], y = p.dy[i];
-        x0 = fminf(x0, x);
-        x1 = fmaxf(x1, x);
-        y0 = fminf(y0, y);
-        y1 = fmaxf(y1, y);
-        zb = max(zb, __float_as_uint(p.dz[i]) & 0x7fffffffu);
-    }
-    s[0][threadIdx.x] = x0;
-    s[1][threadIdx.x] = y0;
-    s[2][threadIdx.x] = x1;
-    s[3][threadIdx.x] = y1;
-    zs[threadIdx.x] = zb;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        const int t = threadIdx.x;
-        if (t < w) {
-            s[0][t] = fminf(s[0][t], s[0][t + w]);
-            s[1][t] = fminf(s[1][t], s[1][t + w]);
-            s[2][t] = fmaxf(s[2][t], s[2][t + w]);
-            s[3][t] = fmaxf(s[3][t], s[3][t + w]);
-            zs[t] = max(zs[t], zs[t + w]);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        hdr[0] = 0.0f;
-        hdr[1] = s[0][0] + 0.5f * (s[2][0] - s[0][0]);
-        hdr[2] = s[1][0] + 0.5f * (s[3][0] - s[1][0]);
-        zmax[0] = __uint_as_float(zs[0]);
-    }
-}
-
-// Centred copy x' = x - c_x, y' = y - c_y, |p'|^2 = fma(y', y', x' x'), and
-// the maximum of |p'|^2 into hdr[0] (bit patterns of non-negative floats
-// order like their values; NaN and inf disable the screen).
-__global__ __launch_bounds__(256) void aidw_prep_centre(ProblemF32 p, float* __restrict__ prep) {
-    __shared__ unsigned s[256];
-    const float cx = prep[1], cy = prep[2];
-    float* X = prep + kPrepHeader;
-    float* Y = X + p.prep_stride;
-    float* P = Y + p.prep_stride;
-    unsigned v = 0;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < p.m; i += gridDim.x * 256) {
-        const float x = p.dx[i] - cx, y = p.dy[i] - cy;
-        const float pp = fmaf(y, y, x * x);
-        X[i] = x;
-        Y[i] = y;
-        P[i] = pp;
-        v = max(v, __float_as_uint(pp) & 0x7fffffffu);
-    }
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicMax(reinterpret_cast<unsigned*>(prep), s[0]);
 }
 
 __global__ __launch_bounds__(256) void aidw_abs_max_tasks(const AbsMaxTask* __restrict__ tasks) {
@@ -864,15 +720,6 @@ hipError_t launch_aidw_f32(const ProblemF32& p, const LaunchF32& cfg, const Spli
 
 hipError_t launch_abs_max(const float* z, int m, float* out, hipStream_t s) {
     hipLaunchKernelGGL(aidw_abs_max, dim3(1), dim3(1024), 0, s, z, m, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_prep(const ProblemF32& p, float* prep, float* zmax, hipStream_t s) {
-    ProblemF32 q = p;
-    q.prep_stride = prep_stride_for(p.m);
-    hipLaunchKernelGGL(aidw_prep_stats, dim3(1), dim3(1024), 0, s, q, prep, zmax);
-    const unsigned blocks = (unsigned)std::min<int64_t>(2048, ((int64_t)p.m + 255) / 256);
-    hipLaunchKernelGGL(aidw_prep_centre, dim3(blocks), dim3(256), 0, s, q, prep);
     return hipGetLastError();
 }
 

@@ -391,7 +391,7 @@ def test_whole_power_weights_in_range(ctx, torch, coord_scale, z_scale, power):
     assert err.max() <= TOL_F32
 
 
-# ---- the screened pass 1 keeps exactly the full scan's k nearest ---------------------
+# ---- tracked and untracked pass 1 keep the same k nearest ----------------------------
 
 def _r_obs_alpha(ctx, torch, inst, track):
     data_xy, data_z, query_xy = aidw.to_device(inst)
@@ -410,8 +410,9 @@ def _r_obs_alpha(ctx, torch, inst, track):
 
 @pytest.mark.parametrize("case", ["offset", "tiny", "clustered", "duplicates", "line"])
 @pytest.mark.parametrize("k", [1, 7, 32])
-def test_screened_pass1_equals_direct_scan(ctx, torch, case, k):
-    # kNN-index tracking forces the direct scan; without it pass 1 is screened
+def test_untracked_pass1_equals_tracked_scan(ctx, torch, case, k):
+    # kNN-index tracking runs the (d^2, index) list and never splits m; without
+    # it the list holds distances only and m may be split into segments
     rng = np.random.default_rng(k * 31 + len(case))
     m, n = 9000, 1500
     if case == "offset":  # large coordinates, small spread: strong cancellation
