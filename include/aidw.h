@@ -203,10 +203,9 @@ aidw_status aidw_tune_load(aidw_t h, const char* path);
 /* ---- Batches: many independent problems in one launch ----------------------
  * Every problem must be AIDW_FP32_SCALED and may not request knn_idx.  The
  * (problem, 64-query tile) work items are ordered longest-first (by m) and
- * claimed by the waves of one fixed-size grid through an atomic counter,
- * so problems of very uneven size share the GPU.  Results per query are
- * bit-identical to aidw_interpolate_ex on the same problem with
- * q_per_lane = 1 and no split. */
+ * run one per wave in a single launch, so problems of very uneven size share
+ * the GPU.  Results per query are bit-identical to aidw_interpolate_ex on
+ * the same problem with q_per_lane = 1 and no split. */
 typedef struct aidw_batch* aidw_batch_t;
 
 /* Validate the problems, upload the work list and capture the launch as a
@@ -218,7 +217,7 @@ aidw_status aidw_batch_create(aidw_t h, const aidw_problem* problems, int count,
 
 /* Replay the captured graph on the handle's current stream (synchronous
  * unless flags has AIDW_FLAG_ASYNC).  Launches of one batch must not
- * overlap: they share the batch's claim counter. */
+ * overlap: they share the batch's per-problem max-|z| slots. */
 aidw_status aidw_batch_launch(aidw_batch_t b, unsigned flags);
 
 /* Free the batch's device memory and graph (waits for the handle's stream). */

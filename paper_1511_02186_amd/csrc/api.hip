@@ -44,7 +44,7 @@ struct aidw_batch {
     aidw_t h = nullptr;
     int count = 0;
     aidw::BatchLaunch launch{};
-    void* device_block = nullptr;  // problems, items and counter
+    void* device_block = nullptr;  // problems, items, max-|z| tasks and slots
     size_t device_bytes = 0;
     hipStream_t capture_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -508,13 +508,13 @@ aidw_status batch_build(aidw_t h, const aidw_problem* problems, int count, aidw_
                      [&](const aidw::BatchItem& x, const aidw::BatchItem& y) {
                          return probs[x.problem].m > probs[y.problem].m;
                      });
-    // device block: problems | items | counter | max-|z| tasks | max-|z| slots
+    // device block: problems | items | max-|z| tasks | max-|z| slots
     const size_t a = 256;
     auto up = [&](size_t v) { return (v + a - 1) / a * a; };
     const size_t sz_p = up(sizeof(aidw::ProblemF32) * probs.size());
     const size_t sz_i = up(sizeof(aidw::BatchItem) * items.size());
     const size_t sz_t = up(sizeof(aidw::AbsMaxTask) * probs.size());
-    const size_t o_t = sz_p + sz_i + a, o_z = o_t + sz_t;
+    const size_t o_t = sz_p + sz_i, o_z = o_t + sz_t;
     const size_t bytes = o_z + up(sizeof(float) * probs.size());
     aidw_status st = device_alloc(h, bytes, &b->device_block);
     if (st != AIDW_OK) return st;
@@ -539,16 +539,10 @@ aidw_status batch_build(aidw_t h, const aidw_problem* problems, int count, aidw_
     b->count = count;
     b->launch.problems = reinterpret_cast<const aidw::ProblemF32*>(base);
     b->launch.items = reinterpret_cast<const aidw::BatchItem*>(base + sz_p);
-    b->launch.counter = reinterpret_cast<int*>(base + sz_p + sz_i);
     b->launch.tasks = reinterpret_cast<const aidw::AbsMaxTask*>(base + o_t);
     b->launch.n_tasks = (int)tasks.size();
     b->launch.n_items = (int)items.size();
     b->launch.K = aidw::k_bucket(kmax);
-    int per_cu = aidw::batch_blocks_per_cu(b->launch.K);
-    if (per_cu <= 0) per_cu = 2;
-    const int64_t groups_needed = ((int64_t)items.size() + aidw::kWavesPerGroup - 1) / aidw::kWavesPerGroup;
-    b->launch.groups = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * h->cu_count,
-                                                                     groups_needed));
     return AIDW_OK;
 }
 

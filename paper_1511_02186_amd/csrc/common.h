@@ -93,8 +93,6 @@ struct BatchItem {
     int base;  // first query of the tile
 };
 
-// A batched launch: `groups` workgroups of kGroupSize threads whose waves
-// claim items[0..n_items) through `counter` (reset by the launch itself).
 // max |z| of one problem's data into *out (each problem's zmax slot).
 struct AbsMaxTask {
     const float* z;
@@ -102,14 +100,14 @@ struct AbsMaxTask {
     int m;
 };
 
+// A batched launch: one wave per item; the hardware dispatches workgroups in
+// index order, so items sorted longest first start longest first.
 struct BatchLaunch {
     const ProblemF32* problems;  // device array
     const BatchItem* items;      // device array, longest first
-    int* counter;                // device int
     const AbsMaxTask* tasks;     // device array, one per problem (fills problems[i].zmax)
     int n_tasks;
     int n_items;
-    int groups;
     int K;                       // register bucket >= every problem's k
 };
 
@@ -134,14 +132,13 @@ struct ServeItem {
     int seg;    // data segment (split phases)
 };
 
+// One launch per tick, one wave per item.
 struct ServeLaunch {
     const ServeJob* jobs;       // device array
     const ServeItem* items;     // device array
-    int* counter;               // device int, reset by the launch
     const AbsMaxTask* tasks;    // device array, one per job (fills jobs[i].p.zmax)
     int n_tasks;
     int n_items;
-    int groups;
     int K;
 };
 
@@ -183,13 +180,10 @@ hipError_t launch_grid_knn_all(const ProblemF32& p, const GridWorkspace& ws, hip
 // ratio: the split path's pass-2 kernels (sp.tiles is set here).
 hipError_t launch_aidw_f32_pass2(const ProblemF32& p, SplitPlan sp, const float* qpar,
                                  double* psum, hipStream_t stream);
-int serve_blocks_per_cu(int K);
 
 hipError_t launch_aidw_f32(const ProblemF32& p, const LaunchF32& cfg, const SplitPlan* sp,
                            const SplitWorkspace* ws, hipStream_t stream);
 hipError_t launch_aidw_f32_batch(const BatchLaunch& b, hipStream_t stream);
-// Resident workgroups per CU of the batched kernel for register bucket K.
-int batch_blocks_per_cu(int K);
 hipError_t launch_aidw_f64(const ProblemF64& p, hipStream_t stream);
 // Data-access variants (0 scalar, 1 LDS tiles, 2 per-lane loads) x layouts
 // (0 SoA, 1 AoaS packed into `aos`, m float4), same arithmetic.

@@ -33,9 +33,9 @@
 //
 // Three drivers share these building blocks:
 //  * aidw_f32_fused: one wave per tile, both passes over all m points;
-//  * aidw_f32_batch: a fixed-size grid whose waves claim (problem, tile)
-//    items from a longest-first work list through an atomic counter, so one
-//    launch (capturable in a hipGraph) serves many problems of uneven size;
+//  * aidw_f32_batch: one wave per (problem, tile) item of a longest-first
+//    work list, so one launch (capturable in a hipGraph) serves many
+//    problems of uneven size;
 //  * split-m: when n is too small to fill the device, the m points are cut
 //    into S segments; one launch computes per-segment k-nearest lists, a
 //    merge kernel turns them into alpha, a third launch computes
@@ -367,23 +367,15 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_fused(ProblemF32 p) {
     fused_tile<K, Q, TRACK>(p, wave_id() * Q * kWaveSize);
 }
 
-// ---- batched: waves claim (problem, tile) items ------------------------------
+// ---- batched: one wave per (problem, tile) item -------------------------------
 template <int K>
 __global__ __launch_bounds__(kGroupSize) void aidw_f32_batch(const ProblemF32* __restrict__ probs,
                                                              const BatchItem* __restrict__ items,
-                                                             int n_items, int* __restrict__ counter) {
-    for (;;) {
-        int it = 0;
-        if (lane_id() == 0) it = atomicAdd(counter, 1);
-        it = __builtin_amdgcn_readfirstlane(it);
-        if (it >= n_items) break;
-        const BatchItem w = items[it];
-        fused_tile<K, 1, false>(probs[w.problem], w.base);
-    }
-}
-
-__global__ void aidw_reset_counter(int* __restrict__ counter) {
-    if (threadIdx.x == 0) *counter = 0;
+                                                             int n_items) {
+    const int it = wave_id();
+    if (it >= n_items) return;
+    const BatchItem w = items[it];
+    fused_tile<K, 1, false>(probs[w.problem], w.base);
 }
 
 // Per-segment k-nearest lists keep only the k real entries of each list,
@@ -584,15 +576,11 @@ __device__ __forceinline__ void serve_item(const ServeJob& J, const ServeItem& i
 template <int K>
 __global__ __launch_bounds__(kGroupSize) void aidw_f32_serve(const ServeJob* __restrict__ jobs,
                                                              const ServeItem* __restrict__ items,
-                                                             int n_items, int* __restrict__ counter) {
-    for (;;) {
-        int it = 0;
-        if (lane_id() == 0) it = atomicAdd(counter, 1);
-        it = __builtin_amdgcn_readfirstlane(it);
-        if (it >= n_items) break;
-        const ServeItem w = items[it];
-        serve_item<K>(jobs[w.job], w);
-    }
+                                                             int n_items) {
+    const int it = wave_id();
+    if (it >= n_items) return;
+    const ServeItem w = items[it];
+    serve_item<K>(jobs[w.job], w);
 }
 
 // ---- host-side launchers ----------------------------------------------------------
@@ -656,42 +644,22 @@ hipError_t launch_single_k(const ProblemF32& p, const LaunchF32& cfg, const Spli
 
 template <int K>
 hipError_t launch_batch_k(const BatchLaunch& b, hipStream_t stream) {
-    hipLaunchKernelGGL(aidw_reset_counter, dim3(1), dim3(64), 0, stream, b.counter);
     if (b.n_tasks > 0)
         hipLaunchKernelGGL(aidw_abs_max_tasks, dim3((unsigned)b.n_tasks), dim3(256), 0, stream,
                            b.tasks);
-    hipLaunchKernelGGL((aidw_f32_batch<K>), dim3(b.groups), dim3(kGroupSize), 0, stream,
-                       b.problems, b.items, b.n_items, b.counter);
+    hipLaunchKernelGGL((aidw_f32_batch<K>), dim3(groups_for(b.n_items)), dim3(kGroupSize), 0,
+                       stream, b.problems, b.items, b.n_items);
     return hipGetLastError();
-}
-
-template <int K>
-int batch_occupancy_k() {
-    int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, aidw_f32_batch<K>, kGroupSize, 0) !=
-        hipSuccess)
-        return 0;
-    return blocks;
 }
 
 template <int K>
 hipError_t launch_serve_k(const ServeLaunch& sl, hipStream_t stream) {
-    hipLaunchKernelGGL(aidw_reset_counter, dim3(1), dim3(64), 0, stream, sl.counter);
     if (sl.n_tasks > 0)
         hipLaunchKernelGGL(aidw_abs_max_tasks, dim3((unsigned)sl.n_tasks), dim3(256), 0, stream,
                            sl.tasks);
-    hipLaunchKernelGGL((aidw_f32_serve<K>), dim3(sl.groups), dim3(kGroupSize), 0, stream, sl.jobs,
-                       sl.items, sl.n_items, sl.counter);
+    hipLaunchKernelGGL((aidw_f32_serve<K>), dim3(groups_for(sl.n_items)), dim3(kGroupSize), 0,
+                       stream, sl.jobs, sl.items, sl.n_items);
     return hipGetLastError();
-}
-
-template <int K>
-int serve_occupancy_k() {
-    int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, aidw_f32_serve<K>, kGroupSize, 0) !=
-        hipSuccess)
-        return 0;
-    return blocks;
 }
 
 #define AIDW_K_DISPATCH(K_RUNTIME, CALL) \
@@ -754,20 +722,6 @@ hipError_t launch_aidw_f32_serve(const ServeLaunch& sl, hipStream_t stream) {
     AIDW_K_DISPATCH(sl.K, CALL)
 #undef CALL
     return hipErrorInvalidValue;
-}
-
-int serve_blocks_per_cu(int K) {
-#define CALL(KK) serve_occupancy_k<KK>()
-    AIDW_K_DISPATCH(K, CALL)
-#undef CALL
-    return 0;
-}
-
-int batch_blocks_per_cu(int K) {
-#define CALL(KK) batch_occupancy_k<KK>()
-    AIDW_K_DISPATCH(K, CALL)
-#undef CALL
-    return 0;
 }
 
 }  // namespace aidw

@@ -56,7 +56,6 @@ class HipExecutor : public sv::Executor {
     size_t arena_bytes = 0;
     std::unordered_map<uint64_t, JobRec> jobs;
     std::vector<Slot> slots;
-    int blocks_per_cu[33] = {0};
     aidw_status error = AIDW_OK;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
@@ -94,12 +93,12 @@ class HipExecutor : public sv::Executor {
             const sv::Item& it = plan.items[i];
             items[i] = aidw::ServeItem{index[it.ticket], it.phase, it.tile, it.seg};
         }
-        // staging: jobs | items | counter | max-|z| tasks | max-|z| slots (one per job,
+        // staging: jobs | items | max-|z| tasks | max-|z| slots (one per job,
         // recomputed by every tick that carries the job, on the tick's own stream)
         const size_t b_jobs = align_up(sizeof(aidw::ServeJob) * sj.size());
         const size_t b_items = align_up(sizeof(aidw::ServeItem) * items.size());
         const size_t b_tasks = align_up(sizeof(aidw::AbsMaxTask) * sj.size());
-        const size_t o_tasks = b_jobs + b_items + kAlign, o_z = o_tasks + b_tasks;
+        const size_t o_tasks = b_jobs + b_items, o_z = o_tasks + b_tasks;
         const size_t bytes = o_z + align_up(sizeof(float) * sj.size());
         if (grow(s, bytes) != AIDW_OK) return AIDW_ENOMEM;
         char* host = static_cast<char*>(s.host);
@@ -132,15 +131,10 @@ class HipExecutor : public sv::Executor {
         aidw::ServeLaunch sl{};
         sl.jobs = reinterpret_cast<const aidw::ServeJob*>(dev);
         sl.items = reinterpret_cast<const aidw::ServeItem*>(dev + b_jobs);
-        sl.counter = reinterpret_cast<int*>(dev + b_jobs + b_items);
         sl.tasks = reinterpret_cast<const aidw::AbsMaxTask*>(dev + o_tasks);
         sl.n_tasks = (int)tasks.size();
         sl.n_items = (int)items.size();
         sl.K = aidw::k_bucket(K);
-        if (!blocks_per_cu[sl.K]) blocks_per_cu[sl.K] = std::max(1, aidw::serve_blocks_per_cu(sl.K));
-        const int64_t need = ((int64_t)items.size() + aidw::kWavesPerGroup - 1) / aidw::kWavesPerGroup;
-        sl.groups = (int)std::max<int64_t>(
-            1, std::min<int64_t>((int64_t)blocks_per_cu[sl.K] * h->cu_count, need));
         e = aidw::launch_aidw_f32_serve(sl, s.stream);
         if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
         if (e != hipSuccess) {
