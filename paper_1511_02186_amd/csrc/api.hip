@@ -168,9 +168,11 @@ aidw_status ensure_workspace(aidw_t h, size_t bytes) {
 namespace aidw {
 namespace detail {
 
-// Number of data segments for an FP32-scaled problem: enough (tile, segment)
-// waves to give every SIMD about 8 resident waves, with segments of at least
-// kMinSegment points.  1 means the fused kernel.
+// Number of data segments for an FP32-scaled problem.  1 (the fused kernel)
+// whenever the 64-query tiles alone fill at least half of 8 waves per SIMD:
+// the fused kernel overlaps one wave's pass 1 with another's pass 2, which
+// the split launches cannot.  Otherwise enough (tile, segment) waves for
+// about 8 per SIMD, with segments of at least kMinSegment points.
 constexpr int kMinSegment = 2048;
 
 aidw::SplitPlan split_plan_for(const aidw_ctx* h, const aidw_tuning& t, int64_t m, int64_t n) {
@@ -178,7 +180,7 @@ aidw::SplitPlan split_plan_for(const aidw_ctx* h, const aidw_tuning& t, int64_t 
     int want = t.split_segments;
     if (want == 0) {
         const int64_t target = (int64_t)(h->cu_count > 0 ? h->cu_count : 256) * 4 * 8;
-        if (sp.tiles >= target) return sp;
+        if (2 * sp.tiles >= target) return sp;
         want = (int)std::min<int64_t>((target + sp.tiles - 1) / sp.tiles, 1 << 20);
     }
     int64_t seg = (m + want - 1) / want;
