@@ -89,6 +89,10 @@ typedef struct aidw_options {
     int device;                        /* HIP device ordinal */
     aidw_precision default_precision;  /* used by aidw_interpolate() */
     size_t hbm_budget_bytes;           /* cap on library-owned device memory; 0 = none */
+    const char* tune_path;             /* host string or NULL: a file written by
+                                          aidw_tune_save, loaded at creation (a
+                                          missing file is ignored, an invalid one
+                                          fails creation with AIDW_EINVAL) */
 } aidw_options;
 
 typedef struct aidw_ctx* aidw_t;
@@ -287,6 +291,14 @@ typedef struct aidw_job {
  * whose workspace can never fit the arena is accepted and reported as
  * failed with AIDW_ENOMEM by aidw_poll. */
 aidw_status aidw_submit(aidw_server_t s, const aidw_job* job, uint64_t* ticket);
+/* Validate and enqueue `count` jobs at once (host array jobs[count]);
+ * tickets[i] identifies jobs[i].  All or nothing: if any job is invalid (the
+ * error names its index) or names an unknown data set, none is enqueued and
+ * every ticket is 0.  Jobs submitted together reach the scheduler together,
+ * so they share ticks as far as the arena and the tick quota allow.
+ * Thread-safe. */
+aidw_status aidw_submit_batch(aidw_server_t s, const aidw_job* jobs, int count,
+                              uint64_t* tickets);
 /* AIDW_EAGAIN while the job is queued or running.  Once it has finished,
  * returns AIDW_OK with *job_status (AIDW_OK or the job's error) and
  * *latency_s (seconds from submission to completion), then forgets the

@@ -39,7 +39,7 @@ AIDW_KMAX = 32
 
 class aidw_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("default_precision", ctypes.c_int),
-                ("hbm_budget_bytes", ctypes.c_size_t)]
+                ("hbm_budget_bytes", ctypes.c_size_t), ("tune_path", ctypes.c_char_p)]
 
 
 class aidw_problem(ctypes.Structure):
@@ -142,6 +142,8 @@ _SIGNATURES = {
     "aidw_server_destroy": (None, [ctypes.c_void_p]),
     "aidw_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_job),
                                    ctypes.POINTER(ctypes.c_uint64)]),
+    "aidw_submit_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_job), ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_uint64)]),
     "aidw_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
                                  ctypes.POINTER(ctypes.c_double)]),
     "aidw_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double,
@@ -185,9 +187,10 @@ def check(status: int) -> int:
 # ---- the C entry points, same names ---------------------------------------
 
 def aidw_create(device: int = 0, default_precision: int = AIDW_FP32_SCALED,
-                hbm_budget_bytes: int = 0) -> int:
+                hbm_budget_bytes: int = 0, tune_path=None) -> int:
     h = ctypes.c_void_p()
-    opt = aidw_options(device, default_precision, hbm_budget_bytes)
+    opt = aidw_options(device, default_precision, hbm_budget_bytes,
+                       None if tune_path is None else os.fsencode(tune_path))
     check(lib().aidw_create(ctypes.byref(h), ctypes.byref(opt)))
     return h.value
 
@@ -305,6 +308,15 @@ def aidw_submit(s, job: aidw_job) -> int:
     return t.value
 
 
+def aidw_submit_batch(s, jobs):
+    """Tickets of the jobs, submitted all or none (raises AidwError)."""
+    n = len(jobs)
+    arr = (aidw_job * max(n, 1))(*jobs)
+    tickets = (ctypes.c_uint64 * max(n, 1))()
+    check(lib().aidw_submit_batch(s, arr, n, tickets))
+    return [tickets[i] for i in range(n)]
+
+
 def aidw_poll(s, ticket):
     """(status, job_status, latency_s); status AIDW_EAGAIN while pending."""
     js, lat = ctypes.c_int(), ctypes.c_double()
@@ -330,9 +342,9 @@ class Context:
     """Owns one aidw handle bound to a device and torch's current stream."""
 
     def __init__(self, device: int = 0, default_precision: int = AIDW_FP32_SCALED,
-                 hbm_budget_bytes: int = 0):
+                 hbm_budget_bytes: int = 0, tune_path=None):
         self.device = device
-        self.h = aidw_create(device, default_precision, hbm_budget_bytes)
+        self.h = aidw_create(device, default_precision, hbm_budget_bytes, tune_path)
 
     def close(self):
         if self.h:

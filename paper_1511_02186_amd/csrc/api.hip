@@ -348,6 +348,13 @@ aidw_status aidw_create(aidw_t* out, const aidw_options* opt) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, o.device) == hipSuccess)
         h->cu_count = cus;
+    if (o.tune_path) {
+        const aidw_status st = aidw_tune_load(h, o.tune_path);
+        if (st != AIDW_OK && st != AIDW_ENOTFOUND) {
+            delete h;
+            return st;  // the message of aidw_tune_load stays
+        }
+    }
     *out = h;
     return AIDW_OK;
 }

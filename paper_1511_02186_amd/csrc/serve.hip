@@ -12,6 +12,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -219,6 +220,65 @@ struct aidw_server {
     }
 };
 
+namespace {
+
+// Validate one job and build its record and scheduler spec (no server lock).
+aidw_status prepare_job(aidw_server* s, const aidw_job* job, JobRec* out, sv::JobSpec* spec_out) {
+    aidw_problem p;
+    memset(&p, 0, sizeof p);
+    p.precision = AIDW_FP32_SCALED;
+    p.data_xy = job->data_xy;
+    p.data_z = job->data_z;
+    p.m = job->m;
+    p.area = job->area;
+    aidw_t h = s->h;
+    if (job->dataset) {
+        std::lock_guard<std::mutex> lk(h->mu);
+        auto it = h->datasets.find(job->dataset);
+        if (it == h->datasets.end())
+            return fail(AIDW_ENOTFOUND, "no dataset %llu", (unsigned long long)job->dataset);
+        p.data_xy = it->second.xy;
+        p.data_z = it->second.z;
+        p.m = it->second.m;
+        p.area = it->second.area;
+    }
+    p.query_xy = job->query_xy;
+    p.n = job->n;
+    p.k = job->k;
+    for (int i = 0; i < 5; ++i) p.alpha_levels[i] = job->alpha_levels[i];
+    p.R_min = job->R_min;
+    p.R_max = job->R_max;
+    p.out = job->out;
+    p.r_obs = job->r_obs;
+    p.alpha = job->alpha;
+    aidw_status st = validate(&p);
+    if (st != AIDW_OK) return st;
+
+    JobRec r;
+    r.p = problem_f32(&p);
+    r.K = aidw::k_bucket(p.k);
+    r.sp = aidw::SplitPlan{1, (int)p.m, (int)((p.n + 63) / 64)};
+    sv::JobSpec spec;
+    spec.m = p.m;
+    spec.n = p.n;
+    const int64_t seg = (s->opt.segment_points + 31) / 32 * 32;
+    if (p.m > seg && p.n > 0) {
+        r.sp.seg_len = (int)seg;
+        r.sp.segments = (int)((p.m + seg - 1) / seg);
+        r.counters_off = align_up(split_workspace_bytes(r.sp, p.k, p.n, nullptr, nullptr));
+        r.ws_bytes = r.counters_off + 2 * sizeof(int) * (size_t)r.sp.tiles;
+        spec.segments = r.sp.segments;
+        spec.seg_len = seg;
+        spec.ws_bytes = r.ws_bytes;
+    }
+    r.dataset = job->dataset;
+    *out = r;
+    *spec_out = spec;
+    return AIDW_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 aidw_status aidw_dataset_register(aidw_t h, const void* data_xy, const void* data_z, int64_t m,
@@ -348,73 +408,46 @@ void aidw_server_destroy(aidw_server_t s) {
 
 aidw_status aidw_submit(aidw_server_t s, const aidw_job* job, uint64_t* ticket) {
     if (!s || !job || !ticket) return fail(AIDW_EINVAL, "server, job or ticket is NULL");
-    *ticket = 0;
-    aidw_problem p;
-    memset(&p, 0, sizeof p);
-    p.precision = AIDW_FP32_SCALED;
-    p.data_xy = job->data_xy;
-    p.data_z = job->data_z;
-    p.m = job->m;
-    p.area = job->area;
-    aidw_t h = s->h;
-    if (job->dataset) {
-        std::lock_guard<std::mutex> lk(h->mu);
-        auto it = h->datasets.find(job->dataset);
-        if (it == h->datasets.end())
-            return fail(AIDW_ENOTFOUND, "no dataset %llu", (unsigned long long)job->dataset);
-        p.data_xy = it->second.xy;
-        p.data_z = it->second.z;
-        p.m = it->second.m;
-        p.area = it->second.area;
-    }
-    p.query_xy = job->query_xy;
-    p.n = job->n;
-    p.k = job->k;
-    for (int i = 0; i < 5; ++i) p.alpha_levels[i] = job->alpha_levels[i];
-    p.R_min = job->R_min;
-    p.R_max = job->R_max;
-    p.out = job->out;
-    p.r_obs = job->r_obs;
-    p.alpha = job->alpha;
-    aidw_status st = validate(&p);
-    if (st != AIDW_OK) return st;
+    return aidw_submit_batch(s, job, 1, ticket);
+}
 
-    JobRec r;
-    r.p = problem_f32(&p);
-    r.K = aidw::k_bucket(p.k);
-    r.sp = aidw::SplitPlan{1, (int)p.m, (int)((p.n + 63) / 64)};
-    sv::JobSpec spec;
-    spec.m = p.m;
-    spec.n = p.n;
-    const int64_t seg = (s->opt.segment_points + 31) / 32 * 32;
-    if (p.m > seg && p.n > 0) {
-        r.sp.seg_len = (int)seg;
-        r.sp.segments = (int)((p.m + seg - 1) / seg);
-        r.counters_off = align_up(split_workspace_bytes(r.sp, p.k, p.n, nullptr, nullptr));
-        r.ws_bytes = r.counters_off + 2 * sizeof(int) * (size_t)r.sp.tiles;
-        spec.segments = r.sp.segments;
-        spec.seg_len = seg;
-        spec.ws_bytes = r.ws_bytes;
+aidw_status aidw_submit_batch(aidw_server_t s, const aidw_job* jobs, int count,
+                              uint64_t* tickets) {
+    if (!s || count < 0 || (count > 0 && (!jobs || !tickets)))
+        return fail(AIDW_EINVAL, "server, jobs or tickets is NULL, or count < 0");
+    for (int i = 0; i < count; ++i) tickets[i] = 0;
+    std::vector<JobRec> recs((size_t)count);
+    std::vector<sv::JobSpec> specs((size_t)count);
+    for (int i = 0; i < count; ++i) {
+        const aidw_status st = prepare_job(s, &jobs[i], &recs[(size_t)i], &specs[(size_t)i]);
+        if (st != AIDW_OK) {
+            const std::string msg = aidw_last_error();
+            return count == 1 ? fail(st, "%s", msg.c_str())
+                              : fail(st, "job %d: %s", i, msg.c_str());
+        }
     }
-    r.dataset = job->dataset;
+    aidw_t h = s->h;
     std::lock_guard<std::mutex> lk(s->mu);
-    if (job->dataset) {
+    {
+        // data sets may have been released since validation: check them all,
+        // then take every reference, so that either all jobs enter or none
         std::lock_guard<std::mutex> lk2(h->mu);
-        auto it = h->datasets.find(job->dataset);
-        if (it == h->datasets.end())
-            return fail(AIDW_ENOTFOUND, "no dataset %llu", (unsigned long long)job->dataset);
-        ++it->second.refs;
+        for (int i = 0; i < count; ++i) {
+            const uint64_t d = recs[(size_t)i].dataset;
+            if (d && h->datasets.find(d) == h->datasets.end())
+                return fail(AIDW_ENOTFOUND, "job %d: no dataset %llu", i, (unsigned long long)d);
+        }
+        for (int i = 0; i < count; ++i)
+            if (recs[(size_t)i].dataset) ++h->datasets.find(recs[(size_t)i].dataset)->second.refs;
     }
-    const uint64_t t = s->sched->submit(spec);
-    sv::JobState state;
-    s->sched->poll(t, &state, nullptr, nullptr);
-    if (state == sv::JobState::Failed) {
-        s->ex.jobs[t] = r;
-        s->ex.retire(t, -2);  // drops the dataset reference
-    } else {
-        s->ex.jobs[t] = r;
+    for (int i = 0; i < count; ++i) {
+        const uint64_t t = s->sched->submit(specs[(size_t)i]);
+        sv::JobState state;
+        s->sched->poll(t, &state, nullptr, nullptr);
+        s->ex.jobs[t] = recs[(size_t)i];
+        if (state == sv::JobState::Failed) s->ex.retire(t, -2);  // drops the dataset reference
+        tickets[i] = t;
     }
-    *ticket = t;
     s->cv.notify_one();
     return AIDW_OK;
 }

@@ -59,10 +59,11 @@ def test_struct_layout_matches_header():
 #include <stdio.h>
 #include "aidw.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(aidw_problem),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(aidw_problem),
          offsetof(aidw_problem, m), offsetof(aidw_problem, k), offsetof(aidw_problem, alpha_levels),
          offsetof(aidw_problem, area), offsetof(aidw_problem, out), offsetof(aidw_problem, knn_idx),
-         offsetof(aidw_problem, flags), sizeof(aidw_options), offsetof(aidw_options, hbm_budget_bytes));
+         offsetof(aidw_problem, flags), sizeof(aidw_options), offsetof(aidw_options, hbm_budget_bytes),
+         offsetof(aidw_options, tune_path));
   return 0;
 }
 """
@@ -76,5 +77,5 @@ int main(void) {
     P, O = aidw.aidw_problem, aidw.aidw_options
     want = [ctypes.sizeof(P), P.m.offset, P.k.offset, P.alpha_levels.offset, P.area.offset,
             P.out.offset, P.knn_idx.offset, P.flags.offset, ctypes.sizeof(O),
-            O.hbm_budget_bytes.offset]
+            O.hbm_budget_bytes.offset, O.tune_path.offset]
     assert got == want

@@ -201,6 +201,39 @@ def test_invalid_job_is_rejected_at_submit(ctx, torch):
         aidw.aidw_server_destroy(srv)
 
 
+def test_submit_batch_all_or_nothing(ctx, torch):
+    insts = mixed(11, 12)
+    jobs = [Job(torch, i) for i in insts]
+    srv = aidw.aidw_server_create(ctx.h, arena_bytes=256 << 20, segment_points=SEG)
+    try:
+        bad = [j.spec() for j in jobs]
+        bad[5].k = 0  # invalid: nothing may be enqueued
+        with pytest.raises(aidw.AidwError) as ei:
+            aidw.aidw_submit_batch(srv, bad)
+        assert ei.value.status == aidw.AIDW_EINVAL
+        assert "job 5" in aidw.last_error()
+        st, stats = aidw.aidw_server_stats(srv)
+        assert stats["submitted"] == 0
+        tickets = aidw.aidw_submit_batch(srv, [j.spec() for j in jobs])
+        assert len(set(tickets)) == len(jobs) and 0 not in tickets
+        for t in tickets:
+            st, js, _ = aidw.aidw_wait(srv, t, 60.0)
+            assert st == aidw.AIDW_OK and js == aidw.AIDW_OK
+    finally:
+        aidw.aidw_server_destroy(srv)
+    torch.cuda.synchronize()
+    for j in jobs:
+        i = j.inst
+        if i.n == 0:
+            continue
+        solo = alone(ctx, torch, i, i.m > SEG)
+        got = j.out.cpu().numpy()
+        if i.m > SEG:
+            assert rel_err(got, solo, np.abs(solo) + 1e-30).max() <= 1e-6, i.name
+        else:
+            assert np.array_equal(got, solo), i.name
+
+
 def test_concurrent_submitters(ctx, torch):
     insts = mixed(7, 24)
     jobs = [Job(torch, i) for i in insts]

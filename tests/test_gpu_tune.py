@@ -55,6 +55,18 @@ def test_tune_save_load_and_use(torch, tmp_path):
         assert aidw.aidw_tune_load(ctx2.h, other) == aidw.AIDW_EINVAL
     finally:
         ctx2.close()
+    # the same table through aidw_options.tune_path at creation
+    ctx3 = aidw.Context(0, tune_path=path)
+    try:
+        p2 = tmp_path / "again.json"
+        aidw.check(aidw.aidw_tune_save(ctx3.h, p2))
+        assert json.loads(p2.read_text())["entries"] == table["entries"]
+    finally:
+        ctx3.close()
+    aidw.Context(0, tune_path=tmp_path / "missing.json").close()  # a missing file is ignored
+    with pytest.raises(aidw.AidwError) as ei:
+        aidw.Context(0, tune_path=bad)
+    assert ei.value.status == aidw.AIDW_EINVAL
 
 
 def test_tune_rejects_bad_sizes(torch):
