@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--no-grid", action="store_true",
                     help="skip timing pass 1 through the uniform grid (AIDW_FLAG_GRID_KNN)")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the issue-cost probe (SIMD cycles of an FP32 FMA and an exp2)")
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="requests of the Poisson serving run")
     ap.add_argument("--ablation", action="store_true",
@@ -195,6 +197,12 @@ def main():
         result["fp64_plain"] = {"ms": ms64, "pair_evals_per_s": pairs / (ms64 * 1e-3),
                                 "speedup_fp32_scaled_vs_fp64": ms64 / ms}
 
+    if not args.no_probe:
+        c = aidw.aidw_probe_issue_costs(ctx.h)
+        # A stream of FP32 FMAs alone reaches 2 / fma_cycles of the packed-FMA
+        # peak: the ceiling of any kernel built without packed FP32.
+        c["fma_only_frac_of_peak"] = 2.0 / c["fma_cycles"]
+        result["issue_costs"] = c
     if not args.no_grid:
         result["grid_knn"] = bench_grid(ctx, torch, aidw, step_args=(
             data_xy, data_z, query_xy, inst), full_ms=ms, pairs=pairs)

@@ -204,6 +204,23 @@ aidw_status aidw_tune_save(aidw_t h, const char* path);
  * is not a tuning file or holds an invalid entry (the table is unchanged). */
 aidw_status aidw_tune_load(aidw_t h, const char* path);
 
+/* ---- Issue-cost probe --------------------------------------------------------
+ * Not part of the method: a measurement of the device that bounds the FP32
+ * kernels.  Their time is set by how long the instructions occupy a SIMD,
+ * and without packed FP32 (disabled in every kernel of this library) that
+ * is not what the 157.3 TFLOP/s packed-FMA figure assumes.  Runs three short
+ * probe kernels (about 0.1 s) on the handle's stream; each value is SIMD
+ * cycles per wave64 instruction. */
+typedef struct aidw_issue_costs {
+    double fma_cycles;             /* FP32 FMA, FMA-only waves (2.0 would be the packed peak) */
+    double exp_cycles;             /* v_exp_f32, in waves that mix it with FMAs */
+    double exp_cycles_beside_fma;  /* v_exp_f32 when other waves of the SIMD run FMAs */
+    double clock_ghz;              /* clock used for the conversion */
+    int compute_units;
+} aidw_issue_costs;
+
+aidw_status aidw_probe_issue_costs(aidw_t h, aidw_issue_costs* out);
+
 /* ---- Batches: many independent problems in one launch ----------------------
  * Every problem must be AIDW_FP32_SCALED and may not request knn_idx.  The
  * (problem, 64-query tile) work items are ordered longest-first (by m) and

@@ -42,6 +42,12 @@ class aidw_options(ctypes.Structure):
                 ("hbm_budget_bytes", ctypes.c_size_t), ("tune_path", ctypes.c_char_p)]
 
 
+class aidw_issue_costs(ctypes.Structure):
+    _fields_ = [("fma_cycles", ctypes.c_double), ("exp_cycles", ctypes.c_double),
+                ("exp_cycles_beside_fma", ctypes.c_double), ("clock_ghz", ctypes.c_double),
+                ("compute_units", ctypes.c_int)]
+
+
 class aidw_problem(ctypes.Structure):
     _fields_ = [
         ("precision", ctypes.c_int),
@@ -142,6 +148,7 @@ _SIGNATURES = {
     "aidw_server_destroy": (None, [ctypes.c_void_p]),
     "aidw_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_job),
                                    ctypes.POINTER(ctypes.c_uint64)]),
+    "aidw_probe_issue_costs": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_issue_costs)]),
     "aidw_submit_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_job), ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_uint64)]),
     "aidw_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
@@ -306,6 +313,13 @@ def aidw_submit(s, job: aidw_job) -> int:
     t = ctypes.c_uint64()
     check(lib().aidw_submit(s, ctypes.byref(job), ctypes.byref(t)))
     return t.value
+
+
+def aidw_probe_issue_costs(h):
+    """SIMD cycles per wave64 instruction on the handle's device (dict)."""
+    c = aidw_issue_costs()
+    check(lib().aidw_probe_issue_costs(h, ctypes.byref(c)))
+    return {f: getattr(c, f) for f, _ in c._fields_}
 
 
 def aidw_submit_batch(s, jobs):

@@ -444,3 +444,13 @@ def test_untracked_pass1_equals_tracked_scan(ctx, torch, case, k):
     assert np.array_equal(a0, a1)
     # the untracked run may split m into segments: same sums up to FP64 order
     assert np.allclose(o1, o0, rtol=1e-6, atol=1e-30)
+
+
+def test_issue_cost_probe_is_plausible(ctx, torch):
+    c = aidw.aidw_probe_issue_costs(ctx.h)
+    say("issue costs: %s" % c)
+    assert c["compute_units"] >= 1 and c["clock_ghz"] > 0.5
+    # a wave64 FMA takes at least one pass of a 32-lane pipe and a transcendental more
+    assert 1.5 < c["fma_cycles"] < 8.0
+    assert c["fma_cycles"] < c["exp_cycles"] < 64.0
+    assert 0.0 <= c["exp_cycles_beside_fma"] < 64.0
