@@ -80,8 +80,10 @@ def parse():
                     help="skip timing pass 1 through the uniform grid (AIDW_FLAG_GRID_KNN)")
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the issue-cost probe (SIMD cycles of an FP32 FMA and an exp2)")
-    ap.add_argument("--serve-requests", type=int, default=400,
-                    help="requests of the Poisson serving run")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests of the 2000 req/s Poisson serving run")
+    ap.add_argument("--serve-sweep-requests", type=int, default=200,
+                    help="requests of each lower-rate serving run (250, 500, 1000 req/s)")
     ap.add_argument("--ablation", action="store_true",
                     help="also time the data-access designs (scalar / LDS-tiled / naive loads, "
                          "SoA / AoaS) at the paper's sizes, end to end like its Table 1")
@@ -211,7 +213,8 @@ def main():
     if not args.no_batch:
         result["batched"] = bench_batched(ctx, torch, aidw, workloads)
     if not args.no_serve:
-        result["serving"] = bench_serving(ctx, torch, aidw, workloads, args.serve_requests)
+        result["serving"] = bench_serving_all(torch, aidw, workloads, args.serve_requests,
+                                              args.serve_sweep_requests)
 
     if not args.no_cpu:
         import oracle
@@ -342,22 +345,54 @@ def bench_batched(ctx, torch, aidw, workloads):
             "launch": "hipGraph replay, median of 5"}
 
 
-def bench_serving(ctx, torch, aidw, workloads, count):
-    """Poisson arrivals at 2000 requests/s of jobs with m log-uniform in
-    [4096, 2^20] and n log-uniform in [256, 2^18]; 20 % reuse a data set."""
-    print("bench: serving run (%d requests)" % count, file=sys.stderr, flush=True)
-    reqs, specs = workloads.serving_stream(count=count)
-    gen = torch.Generator(device="cuda").manual_seed(4)
-    data = {}
-    for i, (m, _, _) in enumerate(specs):
-        xy = torch.rand((2, m), device="cuda", generator=gen)
-        data[i] = (xy, (torch.sin(4 * xy[0]) * torch.cos(3 * xy[1])).contiguous())
+def _serving_data(torch, spec, gen):
+    """A serving data set on the device: (data_xy, data_z), area 1.  Uniform
+    points in the unit square, or 90 % from 64 isotropic Gaussians (centres
+    uniform, sigma log-uniform in [1e-4, 1e-1], clamped to the square) plus
+    10 % uniform background; z = sum over the centres of exp(-10 |p - c|^2)."""
+    m, kind, _ = spec
+    xy = torch.rand((2, m), device="cuda", generator=gen)
+    if kind == 0:
+        return xy, (torch.sin(4 * xy[0]) * torch.cos(3 * xy[1])).contiguous()
+    centres = torch.rand((64, 2), device="cuda", generator=gen)
+    sig = torch.exp(torch.empty(64, device="cuda").uniform_(np.log(1e-4), np.log(1e-1),
+                                                            generator=gen))
+    n_mix = int(round(0.9 * m))
+    pick = torch.randint(0, 64, (n_mix,), device="cuda", generator=gen)
+    pts = centres[pick] + sig[pick, None] * torch.randn((n_mix, 2), device="cuda", generator=gen)
+    xy[:, :n_mix] = pts.clamp(0.0, 1.0).t()
+    d2 = ((xy.t()[:, None, :] - centres[None, :, :]) ** 2).sum(-1)
+    return xy.contiguous(), torch.exp(-10.0 * d2).sum(-1).contiguous()
+
+
+def bench_serving(ctx, torch, aidw, workloads, count, rate=2000.0, seed=4):
+    """Poisson arrivals of jobs with m log-uniform in [4096, 2^20] and n
+    log-uniform in [256, 2^18], uniform or clustered points; data sets used
+    by more than one request are registered once (library-owned, resident),
+    the others are passed by pointer.  The handle's HBM budget is 64 GB."""
+    print("bench: serving run (%d requests at %g/s)" % (count, rate), file=sys.stderr, flush=True)
+    reqs, specs = workloads.serving_stream(count=count, rate=rate, seed=seed)
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    uses = {}
+    for r in reqs:
+        uses[r.dataset] = uses.get(r.dataset, 0) + 1
+    data = {i: _serving_data(torch, sp, gen) for i, sp in enumerate(specs)}
+    torch.cuda.synchronize()
+    ids = {}
+    for i, n_use in uses.items():
+        if n_use > 1:
+            xy, z = data[i]
+            ids[i] = aidw.aidw_dataset_register(ctx.h, xy.data_ptr(), z.data_ptr(), z.numel(), 1.0)
     jobs = []
     for r in reqs:
         q = torch.rand((2, r.n), device="cuda", generator=gen)
         out = torch.empty(r.n, device="cuda")
-        xy, z = data[r.dataset]
-        jobs.append((q, out, aidw.make_job(q, r.k, out, data_xy=xy, data_z=z, area=1.0)))
+        if r.dataset in ids:
+            spec = aidw.make_job(q, r.k, out, dataset=ids[r.dataset])
+        else:
+            xy, z = data[r.dataset]
+            spec = aidw.make_job(q, r.k, out, data_xy=xy, data_z=z, area=1.0)
+        jobs.append((q, out, spec))
     torch.cuda.synchronize()
     srv = aidw.aidw_server_create(ctx.h, arena_bytes=16 << 30)
     try:
@@ -373,16 +408,38 @@ def bench_serving(ctx, torch, aidw, workloads, count):
         _, stats = aidw.aidw_server_stats(srv)
     finally:
         aidw.aidw_server_destroy(srv)
+        for d in ids.values():
+            aidw.aidw_dataset_release(ctx.h, d)
     ok = sum(1 for st, js, _ in res if st == aidw.AIDW_OK and js == aidw.AIDW_OK)
     lat = np.array([l for _, _, l in res]) * 1e3
     pairs = float(sum(2.0 * specs[r.dataset][0] * r.n for r in reqs))
     span = reqs[-1].t_arrival
-    return {"workload": "Poisson 2000 req/s, m log-uniform [4096, 2^20], n log-uniform "
-                        "[256, 2^18], k in {8, 10, 15}, 20 % data-set reuse, uniform points",
-            "requests": count, "completed": ok, "wall_s": wall,
+    return {"workload": "Poisson %g req/s, m log-uniform [4096, 2^20], n log-uniform "
+                        "[256, 2^18], k in {8, 10, 15}, uniform or clustered points, "
+                        "20 %% data-set reuse (registered)" % rate,
+            "requests": count, "completed": ok, "registered_datasets": len(ids),
+            "wall_s": wall,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "pair_evals_per_s": pairs / wall, "offered_pair_evals_per_s": pairs / span,
             "ticks": stats["ticks"]}
+
+
+def bench_serving_all(torch, aidw, workloads, count, sweep_count):
+    """The 2000 req/s run, then lower rates toward the knee of the latency
+    curve, on a handle with a 64 GB HBM budget."""
+    ctx = aidw.Context(0, hbm_budget_bytes=64 << 30)
+    try:
+        res = bench_serving(ctx, torch, aidw, workloads, count)
+        sweep = []
+        for rate in (250.0, 500.0, 1000.0):
+            r = bench_serving(ctx, torch, aidw, workloads, sweep_count, rate=rate, seed=40)
+            sweep.append({k: r[k] for k in ("requests", "completed", "p50_ms", "p99_ms",
+                                             "pair_evals_per_s", "offered_pair_evals_per_s")})
+            sweep[-1]["rate"] = rate
+        res["rate_sweep"] = sweep
+        return res
+    finally:
+        ctx.close()
 
 
 if __name__ == "__main__":
