@@ -67,8 +67,11 @@ typedef enum aidw_status {
 typedef enum aidw_precision {
     /* float inputs and output; FP32 pair arithmetic with weights rescaled per
      * query as (d_min^2 / d^2)^(alpha/2) = exp2((alpha/2)(log2 d_min^2 -
-     * log2 d^2)), FP32 partial sums folded into FP64 accumulators, FP64
-     * r_obs / R / mu_R / alpha and final division. */
+     * log2 d^2)), or, where every query of a 64-query tile has the same
+     * whole alpha in [1, 8], rsq(d^2)^alpha (times d_min^alpha unless max|z|
+     * and d_min keep the unscaled sums inside the FP32 range); FP32 partial
+     * sums folded into FP64 accumulators, FP64 r_obs / R / mu_R / alpha and
+     * final division. */
     AIDW_FP32_SCALED = 0,
     /* double inputs and output; plain FP64: d^2 without FMA contraction,
      * weights pow(d, -alpha), compensated FP64 sums. */
@@ -79,11 +82,13 @@ typedef enum aidw_precision {
 #define AIDW_FLAG_ASYNC 1u     /* return once the work is queued on the stream */
 #define AIDW_FLAG_GRID_KNN 2u  /* FP32-scaled: find the k nearest through a uniform grid
                                   over the data (about 2 points per cell) instead of a
-                                  full scan; the k nearest distances, r_obs, alpha and
-                                  the output are bit-identical to the full scan's.
-                                  Pass 2 still sums over all m points.  Not with
-                                  knn_idx.  Uses about 14 m + 32 n bytes of library
-                                  workspace. */
+                                  full scan; the k nearest distances, r_obs and alpha
+                                  are bit-identical to the full scan's, the output
+                                  equal up to the order of its FP64 sums.  Pass 2
+                                  still sums over all m points.  Not with knn_idx,
+                                  FP32-scaled only.  Uses about 14 m + (16 + 16 S) n
+                                  bytes of library workspace (S data segments of
+                                  pass 2, 1 unless there are few queries). */
 
 typedef struct aidw_options {
     int device;                        /* HIP device ordinal */
