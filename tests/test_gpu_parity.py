@@ -454,3 +454,39 @@ def test_issue_cost_probe_is_plausible(ctx, torch):
     assert 1.5 < c["fma_cycles"] < 8.0
     assert c["fma_cycles"] < c["exp_cycles"] < 64.0
     assert 0.0 <= c["exp_cycles_beside_fma"] < 64.0
+
+
+# ---- size limits and malformed pointers (host validation, nothing launched) ----------
+
+@pytest.mark.parametrize("field,value", [("m", 1 << 31), ("m", 0), ("n", 1 << 31), ("n", -1),
+                                         ("misaligned", 1), ("null_out", 0)])
+def test_size_limits_and_pointers_are_validated(ctx, torch, field, value):
+    d = torch.rand(2, 64, device="cuda")
+    z = torch.rand(64, device="cuda")
+    q = torch.rand(2, 8, device="cuda")
+    out = torch.full((8,), 7.0, device="cuda")
+    ctx.bind_current_stream()
+    p = ctx.problem(d, z, q, 4, out, area=1.0)
+    if field == "m":
+        p.m = value
+    elif field == "n":
+        p.n = value
+    elif field == "misaligned":
+        p.data_z = z.data_ptr() + value
+    else:
+        p.out = None
+    assert aidw.aidw_interpolate_ex(ctx.h, p) == aidw.AIDW_EINVAL
+    torch.cuda.synchronize()
+    assert torch.all(out == 7.0)
+
+
+def test_sixteen_million_points_k32(ctx, torch):
+    # m = 2^24 (the data alone 192 MiB), few queries (split into data segments),
+    # the largest k; sampled queries against the oracle
+    inst = workloads.paper_scale(m=1 << 24, n=3000, seed=17, k=32)
+    out = gpu_run(ctx, torch, inst)
+    idx = np.concatenate([np.arange(0, 3000, 97), [2999]])
+    o, scale = ref(inst, idx=idx)
+    err = rel_err(out[idx], o, scale)
+    say("m=2^24 k=32: max err %.3e over %d sampled queries" % (err.max(), len(idx)))
+    assert err.max() <= TOL_F32
