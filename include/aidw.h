@@ -145,7 +145,9 @@ aidw_status aidw_interpolate(aidw_t h, const void* data_xy, const void* data_z, 
                              double area, void* out);
 
 /* AIDW of one problem with an explicit precision, optional per-query
- * diagnostics (r_obs, alpha, kNN indices) and flags. */
+ * diagnostics (r_obs, alpha, kNN indices) and flags.  A call may grow the
+ * handle's workspace (hipMalloc), so it is not meant to be recorded into a
+ * hipGraph; aidw_batch_* captures and replays launches. */
 aidw_status aidw_interpolate_ex(aidw_t h, const aidw_problem* p);
 
 /* Standard IDW (Sec. 2.1, Eq. 1): every query uses the constant power

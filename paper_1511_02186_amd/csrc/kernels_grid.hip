@@ -119,6 +119,15 @@ __device__ __forceinline__ int cell_index(const GridGeom& g, float x, float y) {
     return cell_of(g.gy, y, g.y0, g.inv_ch) * g.gx + cell_of(g.gx, x, g.x0, g.inv_cw);
 }
 
+// Zero the cell counters with a kernel rather than hipMemsetAsync, so that
+// the sequence stays correct if a caller captures it in a hipGraph.
+__global__ void grid_clear(int* __restrict__ counts, int* __restrict__ cursor, int cells) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i <= cells; i += gridDim.x * kBlock) {
+        counts[i] = 0;
+        if (i < cells) cursor[i] = 0;
+    }
+}
+
 __global__ void grid_count(const float* __restrict__ x, const float* __restrict__ y, int m,
                            const GridGeom* __restrict__ geo, int* __restrict__ counts) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -219,16 +228,15 @@ size_t grid_temp_bytes(int cells) {
 hipError_t launch_grid_knn_all(const ProblemF32& p, const GridWorkspace& ws, hipStream_t s) {
     const int cells = ws.cells;
     const int nparts = ws.nparts;
-    hipError_t e = hipMemsetAsync(ws.counts, 0, sizeof(int) * (size_t)(cells + 1), s);
-    if (e == hipSuccess) e = hipMemsetAsync(ws.cursor, 0, sizeof(int) * (size_t)cells, s);
-    if (e != hipSuccess) return e;
+    const unsigned gc = (unsigned)std::min<int64_t>(1024, ((int64_t)cells + kBlock) / kBlock);
+    hipLaunchKernelGGL(grid_clear, dim3(gc), dim3(kBlock), 0, s, ws.counts, ws.cursor, cells);
     hipLaunchKernelGGL(bbox_partial, dim3(nparts), dim3(kBlock), 0, s, p.dx, p.dy, p.m, ws.part);
     hipLaunchKernelGGL(grid_setup, dim3(1), dim3(kBlock), 0, s, ws.part, nparts, cells, ws.geo);
     const unsigned gm = (unsigned)((p.m + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(grid_count, dim3(gm), dim3(kBlock), 0, s, p.dx, p.dy, p.m, ws.geo,
                        ws.counts);
     size_t tb = ws.temp_bytes;
-    e = hipcub::DeviceScan::ExclusiveSum(ws.temp, tb, ws.counts, ws.start, cells + 1, s);
+    hipError_t e = hipcub::DeviceScan::ExclusiveSum(ws.temp, tb, ws.counts, ws.start, cells + 1, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(grid_scatter, dim3(gm), dim3(kBlock), 0, s, p.dx, p.dy, p.m, ws.geo,
                        ws.start, ws.cursor, ws.sorted);
