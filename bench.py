@@ -239,23 +239,26 @@ def main():
 
 def bench_ablation(ctx, torch, aidw, workloads, sizes=(10240, 51200, 102400, 512000, 1024000)):
     """The paper's Table 1 axes on this GPU: m = n = N points in a square,
-    every data-access design and layout, plus the production launch.  Times
+    every data-access design and layout, the production launch and the plain
+    FP64 kernel (FP32 against FP64, as the paper's Table 1 does).  Times
     are kernel-only (HIP events) and end to end (pinned host -> device copy of
     the inputs, kernel, device -> host copy of the output), as in Sec. 4."""
     designs = [("production", None, None)] + [
         ("%s_%s" % (a, l), ai, li)
         for ai, a in enumerate(["scalar", "tiled", "naive"])
-        for li, l in enumerate(["soa", "aoas"])]
+        for li, l in enumerate(["soa", "aoas"])] + [("plain_fp64", None, None)]
     rows = []
     for N in sizes:
         inst = workloads.paper_scale(m=N, n=N, seed=7)
-        host = [torch.from_numpy(a).pin_memory() for a in
-                (inst.data_xy(), inst.data_z.copy(), inst.query_xy())]
-        out_h = torch.empty(N, dtype=torch.float32).pin_memory()
+        inst64 = workloads.paper_scale(m=N, n=N, seed=7, dtype=np.float64)
         for name, acc, lay in designs:
             print("bench: ablation N=%d %s" % (N, name), file=sys.stderr, flush=True)
+            src = inst64 if name == "plain_fp64" else inst
+            host = [torch.from_numpy(a).pin_memory() for a in
+                    (src.data_xy(), src.data_z.copy(), src.query_xy())]
+            out_h = torch.empty(N, dtype=host[0].dtype).pin_memory()
             dev = [h.to("cuda", non_blocking=True) for h in host]
-            out = torch.empty(N, device="cuda")
+            out = torch.empty(N, dtype=host[0].dtype, device="cuda")
             ctx.bind_current_stream()
             p = ctx.problem(dev[0], dev[1], dev[2], inst.k, out, inst.levels, inst.R_min,
                             inst.R_max, inst.area, flags=aidw.AIDW_FLAG_ASYNC)
