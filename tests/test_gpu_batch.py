@@ -1,4 +1,4 @@
-"""Batched launches (many independent problems, one persistent launch, graph
+"""Batched launches (many independent problems, one launch, graph
 replay) and the split-m path for problems with few queries.  All results are
 checked against the FP64 oracle, and batched results against the same
 problems run alone."""
