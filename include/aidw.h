@@ -133,7 +133,8 @@ void aidw_destroy(aidw_t h);
 
 /* Issue subsequent work on `stream` (a hipStream_t of the handle's device,
  * e.g. torch.cuda.current_stream().cuda_stream); NULL selects the default
- * stream. */
+ * stream.  Switching to another stream first waits for the work queued on
+ * the previous one, since later calls reuse the handle's workspace. */
 aidw_status aidw_set_stream(aidw_t h, void* stream);
 
 /* AIDW of n queries over m data points (Eq. 1-6), in the handle's default

@@ -126,16 +126,21 @@ namespace detail {
 aidw_status device_alloc(aidw_t h, size_t bytes, void** out) {
     *out = nullptr;
     if (bytes == 0) return AIDW_OK;
-    if (h->hbm_budget && h->hbm_in_use + bytes > h->hbm_budget)
-        return fail(AIDW_ENOMEM, "device budget exceeded: %zu in use + %zu requested > %zu",
-                    h->hbm_in_use, bytes, h->hbm_budget);
+    {
+        // check and reserve in one step: the serving worker allocates too
+        std::lock_guard<std::mutex> lk(h->mu);
+        if (h->hbm_budget && h->hbm_in_use + bytes > h->hbm_budget)
+            return fail(AIDW_ENOMEM, "device budget exceeded: %zu in use + %zu requested > %zu",
+                        h->hbm_in_use, bytes, h->hbm_budget);
+        h->hbm_in_use += bytes;
+    }
     hipError_t e = hipMalloc(out, bytes);
     if (e != hipSuccess) {
         *out = nullptr;
+        std::lock_guard<std::mutex> lk(h->mu);
+        h->hbm_in_use -= bytes;
         return fail(AIDW_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
     }
-    std::lock_guard<std::mutex> lk(h->mu);
-    h->hbm_in_use += bytes;
     return AIDW_OK;
 }
 

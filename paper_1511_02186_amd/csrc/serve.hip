@@ -173,11 +173,11 @@ class HipExecutor : public sv::Executor {
             if (s.host) (void)hipHostFree(s.host);
             s.host = nullptr;
             s.host_cap = 0;
-            if (hipHostMalloc(&s.host, bytes, hipHostMallocDefault) != hipSuccess) {
+            if (hipHostMalloc(&s.host, bytes * 2, hipHostMallocDefault) != hipSuccess) {
                 s.host = nullptr;
-                return fail(AIDW_ENOMEM, "pinned staging of %zu bytes", bytes);
+                return fail(AIDW_ENOMEM, "pinned staging of %zu bytes", bytes * 2);
             }
-            s.host_cap = bytes;
+            s.host_cap = bytes * 2;
         }
         if (bytes > s.dev_cap) {
             device_free(h, s.dev, s.dev_cap);
