@@ -37,10 +37,10 @@ def say(msg):
     print(msg, flush=True)
 
 
-def gpu_run(ctx, torch, inst, diag=False, q_per_lane=0, query_index=None):
+def gpu_run(ctx, torch, inst, diag=False, q_per_lane=0, query_index=None, split=0, cap=0):
     inst_q = inst if query_index is None else _subset(inst, query_index)
     data_xy, data_z, query_xy = aidw.to_device(inst_q)
-    ctx.set_tuning(q_per_lane)
+    ctx.set_tuning(q_per_lane, cap, split)
     try:
         res = ctx.interpolate(data_xy, data_z, query_xy, inst.k, inst.levels, inst.R_min,
                               inst.R_max, inst.area, diag=diag)
@@ -106,11 +106,13 @@ def test_small_fp32_scaled(ctx, torch):
     assert np.max(np.abs(alpha - o_a)) <= 1e-5
 
 
-@pytest.mark.parametrize("q", [1, 2, 4])
-def test_fp32_launch_shapes_agree(ctx, torch, q):
+@pytest.mark.parametrize("q,cap", [(1, 0), (2, 0), (4, 0), (1, 2), (2, 4)])
+def test_fp32_launch_shapes_agree(ctx, torch, q, cap):
+    # one fused launch (no split of m), so the queries-per-lane and
+    # occupancy-cap variants of the kernel really run
     inst = workloads.paper_scale(m=3001, n=2 * 4 * 256 + 77, seed=21)
-    out = gpu_run(ctx, torch, inst, q_per_lane=q)
-    base = gpu_run(ctx, torch, inst, q_per_lane=1)
+    out = gpu_run(ctx, torch, inst, q_per_lane=q, split=1, cap=cap)
+    base = gpu_run(ctx, torch, inst, q_per_lane=1, split=1)
     # one query per lane may take the one-transcendental pass 2 for waves of
     # a common whole power; the shapes agree to rounding
     assert np.allclose(out, base, rtol=2e-6, atol=1e-6 * np.abs(base).max())
