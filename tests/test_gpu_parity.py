@@ -111,11 +111,14 @@ def test_fp32_launch_shapes_agree(ctx, torch, q, cap):
     # one fused launch (no split of m), so the queries-per-lane and
     # occupancy-cap variants of the kernel really run
     inst = workloads.paper_scale(m=3001, n=2 * 4 * 256 + 77, seed=21)
+    inst.query_x[::41] = inst.data_x[:len(inst.query_x[::41])]  # some queries on data points
+    inst.query_y[::41] = inst.data_y[:len(inst.query_y[::41])]
     out = gpu_run(ctx, torch, inst, q_per_lane=q, split=1, cap=cap)
     base = gpu_run(ctx, torch, inst, q_per_lane=1, split=1)
     # one query per lane may take the one-transcendental pass 2 for waves of
     # a common whole power; the shapes agree to rounding
     assert np.allclose(out, base, rtol=2e-6, atol=1e-6 * np.abs(base).max())
+    assert np.array_equal(out[::41], inst.data_z[:len(out[::41])])  # z_i of the point hit
     o, scale = ref(inst, idx=np.arange(0, inst.n, 7))
     assert rel_err(out[::7], o, scale).max() <= TOL_F32
 
