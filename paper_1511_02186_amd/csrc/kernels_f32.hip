@@ -20,7 +20,9 @@
 //  * Pass-2 weights are rescaled per query so that none exceeds 1:
 //    w = (d_min^2 / d^2)^(alpha/2) = exp2(-(alpha/2) log2 d^2 + (alpha/2) log2 d_min^2),
 //    i.e. one v_log_f32, one FMA and one v_exp_f32 per pair.  The common
-//    factor d_min^(-alpha) cancels in the ratio of Eq. 1.
+//    factor d_min^(-alpha) cancels in the ratio of Eq. 1.  Waves whose
+//    queries share one whole alpha A in [1, 8] use w = rsq(d^2)^A instead
+//    (one transcendental), unscaled when max|z| and d_min allow it.
 //  * Sum w and sum w*z are accumulated in FP32 over each batch of B points
 //    and folded into FP64 accumulators after every batch; the final ratio is
 //    taken in FP64.
@@ -31,7 +33,7 @@
 //    weight exp2(-inf) = 0, so the result is the mean z of the coincident
 //    points.
 //
-// Three drivers share these building blocks:
+// Drivers sharing these building blocks:
 //  * aidw_f32_fused: one wave per tile, both passes over all m points;
 //  * aidw_f32_batch: one wave per (problem, tile) item of a longest-first
 //    work list, so one launch (capturable in a hipGraph) serves many
@@ -39,7 +41,9 @@
 //  * split-m: when n is too small to fill the device, the m points are cut
 //    into S segments; one launch computes per-segment k-nearest lists, a
 //    merge kernel turns them into alpha, a third launch computes
-//    per-segment weighted sums and a last kernel adds the segments in order.
+//    per-segment weighted sums and a last kernel adds the segments in order;
+//  * aidw_f32_serve: fused and split items of many jobs in one launch per
+//    scheduling tick.
 #include "common.h"
 #include "device_math.h"
 
