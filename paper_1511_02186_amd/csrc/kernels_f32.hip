@@ -23,6 +23,13 @@
 //    factor d_min^(-alpha) cancels in the ratio of Eq. 1.  Waves whose
 //    queries share one whole alpha A in [1, 8] use w = rsq(d^2)^A instead
 //    (one transcendental), unscaled when max|z| and d_min allow it.
+//  * Pass 2 with one query per lane is software-pipelined by one batch: the
+//    transcendentals of batch b+1 are issued back to back, as a burst, after
+//    the weights of batch b are summed.  On gfx950 a transcendental keeps the
+//    SIMD from pairing two VALU instructions of different waves in one
+//    issue cycle; spread one per weight, with the weight's next multiply
+//    waiting on it, it cost about 14 cycles of issue per wave instead of the
+//    8 it costs inside a burst.
 //  * Sum w and sum w*z are accumulated in FP32 over each batch of B points
 //    and folded into FP64 accumulators after every batch; the final ratio is
 //    taken in FP64.
@@ -53,9 +60,12 @@ namespace {
 // Data points per scalar-load batch.  Pass 1 loads x and y (2 SGPRs per
 // point), pass 2 also z (3 SGPRs per point); the batch is sized so that the
 // SGPR file holds it without spills.  Lanes that own several queries use
-// smaller batches to leave SGPRs for their extra state.
+// smaller batches to leave SGPRs for their extra state.  Pass 1 keeps B
+// squared distances in VGPRs until the batch minimum is known: 16 keeps the
+// k <= 16 kernels at 64 VGPRs or fewer (8 waves per SIMD), where 32 points
+// took 69 VGPRs (7 waves).
 #ifndef AIDW_F32_B1
-#define AIDW_F32_B1 32
+#define AIDW_F32_B1 16
 #endif
 #ifndef AIDW_F32_B2
 #define AIDW_F32_B2 16
@@ -157,6 +167,105 @@ __device__ __forceinline__ void init_lists(float (&top)[Q][K],
 __device__ __forceinline__ bool coincident(float aL0) { return !(aL0 > -INFINITY); }
 
 // ---- pass 2: weighted sums over data points [j0, j1) -----------------------
+// Pass 2 with one query per lane and a general alpha: w = exp2(na log2(d^2)
+// + aL0).  Software-pipelined by one batch like the whole-power loop: the
+// log2 and exp2 of batch b+1 go out as two bursts after batch b is summed.
+template <bool SAFE>
+__device__ __forceinline__ void scan_wsum1(cptr X, cptr Y, cptr Z, int j0, int j1, float qx,
+                                           float qy, float na, float aL0, double& Sw,
+                                           double& Swz) {
+    constexpr int B = batch2_for<1>();
+    auto from_d2 = [&](const float (&d2)[B], float (&w)[B]) {
+        float l[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) l[u] = __builtin_amdgcn_logf(d2[u]);
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            float t = fmaf(na, l[u], aL0);
+            if (SAFE) t = fminf(t, 0.0f);
+            w[u] = __builtin_amdgcn_exp2f(t);
+        }
+    };
+    auto weights = [&](const float (&px)[B], const float (&py)[B], float (&w)[B]) {
+        float d2[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) d2[u] = sqdist(qx, qy, px[u], py[u]);
+        from_d2(d2, w);
+    };
+    auto sum = [&](const float (&w)[B], const float (&pz)[B]) {
+        float sw = 0.0f, swz = 0.0f;
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            sw += w[u];
+            swz = fmaf(w[u], pz[u], swz);
+        }
+        Sw += (double)sw;
+        Swz += (double)swz;
+    };
+    int j = j0;
+    if (j + 2 * B <= j1) {
+        float w[B];
+        {
+            float px[B], py[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                px[u] = X[j + u];
+                py[u] = Y[j + u];
+            }
+            weights(px, py, w);
+        }
+        for (; j + 2 * B <= j1; j += B) {
+            float pz[B], nx[B], ny[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                pz[u] = Z[j + u];
+                nx[u] = X[j + B + u];
+                ny[u] = Y[j + B + u];
+            }
+            // point by point, as in the whole-power loop: next batch's
+            // distance beside this batch's sums
+            float d2[B], sw = 0.0f, swz = 0.0f;
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                d2[u] = sqdist(qx, qy, nx[u], ny[u]);
+                sw += w[u];
+                swz = fmaf(w[u], pz[u], swz);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            Sw += (double)sw;
+            Swz += (double)swz;
+            from_d2(d2, w);
+        }
+        float pz[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) pz[u] = Z[j + u];
+        sum(w, pz);
+        j += B;
+    }
+    for (; j + B <= j1; j += B) {
+        float px[B], py[B], pz[B], w[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            px[u] = X[j + u];
+            py[u] = Y[j + u];
+            pz[u] = Z[j + u];
+        }
+        weights(px, py, w);
+        sum(w, pz);
+    }
+    for (; j < j1; ++j) {
+        const float d2 = sqdist(qx, qy, X[j], Y[j]);
+        float t = fmaf(na, __builtin_amdgcn_logf(d2), aL0);
+        if (SAFE) t = fminf(t, 0.0f);
+        const float w = __builtin_amdgcn_exp2f(t);
+        Sw += (double)w;
+        Swz += (double)(w * Z[j]);
+    }
+}
+
+// The same for Q queries per lane (the kernels for few query tiles), without
+// the pipelining: their registers are already spent on the Q lists.
 template <int Q, bool SAFE>
 __device__ __forceinline__ void scan_wsum(cptr X, cptr Y, cptr Z, int j0, int j1,
                                           const float (&qx)[Q], const float (&qy)[Q],
@@ -214,44 +323,99 @@ __device__ __forceinline__ float ipow(float s) {
     }
 }
 
+// One batch of whole-power weights from r = rsq(d^2): w = (d_min r)^A, or
+// r^A without SCALED; Σw and Σwz summed in point order in FP32, then added
+// to the FP64 sums.  No fusing of w's last product into sw += w: Σw and Σwz
+// then round alike (a constant field comes out exact).  The explicit fmaf
+// calls stay.
+template <int A, bool SCALED, int B>
+__device__ __forceinline__ void int_batch(const float (&r)[B], const float (&pz)[B], float dmin,
+                                          double& Sw, double& Swz) {
+#pragma clang fp contract(off)
+    auto power = [&](float x) { return ipow<A>(SCALED ? dmin * x : x); };
+    const float w0 = power(r[0]);
+    float sw = w0, swz = w0 * pz[0];
+#pragma unroll
+    for (int u = 1; u < B; ++u) {
+        const float w = power(r[u]);
+        sw += w;
+        swz = fmaf(w, pz[u], swz);
+    }
+    Sw += (double)sw;
+    Swz += (double)swz;
+}
+
 // Pass 2 for a wave whose queries all have the same integer power A and a
 // normal, nonzero d_min: w = (d_min / d)^A = (d_min * rsq(d^2))^A, one
 // transcendental instead of two.  Without SCALED the common factor d_min^-A
 // is left in (w = rsq(d^2)^A, one multiply less per pair); the caller allows
 // that only where every weight and every w*z stays inside the FP32 range.
+//
+// Software-pipelined by one batch: the rsq of batch b+1 go out as one burst
+// after the weights of batch b are summed (15 % less time for this loop at
+// m = n = 2^20 than one rsq beside each weight).
 template <int A, bool SCALED>
 __device__ __forceinline__ void scan_wsum_int(cptr X, cptr Y, cptr Z, int j0, int j1, float qx,
                                               float qy, float dmin, double& Sw, double& Swz) {
-    // No fusing of w's last product into sw += w: Σw and Σwz then round
-    // alike (a constant field comes out exact).  The explicit fmaf calls stay.
 #pragma clang fp contract(off)
     constexpr int B = batch2_for<1>();
-    auto weight = [&](float d2) {
-        const float r = __builtin_amdgcn_rsqf(d2);
-        return ipow<A>(SCALED ? dmin * r : r);
-    };
     int j = j0;
+    if (j + 2 * B <= j1) {
+        float r[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) r[u] = __builtin_amdgcn_rsqf(sqdist(qx, qy, X[j + u], Y[j + u]));
+        for (; j + 2 * B <= j1; j += B) {
+            float pz[B], nx[B], ny[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                pz[u] = Z[j + u];
+                nx[u] = X[j + B + u];
+                ny[u] = Y[j + B + u];
+            }
+            // point by point: the distance of the next batch's point beside
+            // this batch's weight, so that scalar-operand subtractions sit
+            // between plain multiplies (two VALU instructions of different
+            // waves pair in one issue cycle only if at most one reads an
+            // SGPR); the scheduling barriers keep that order
+            float d2[B], sw, swz;
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                d2[u] = sqdist(qx, qy, nx[u], ny[u]);
+                const float w = ipow<A>(SCALED ? dmin * r[u] : r[u]);
+                if (u == 0) {
+                    sw = w;
+                    swz = w * pz[0];
+                } else {
+                    sw += w;
+                    swz = fmaf(w, pz[u], swz);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            Sw += (double)sw;
+            Swz += (double)swz;
+#pragma unroll
+            for (int u = 0; u < B; ++u) r[u] = __builtin_amdgcn_rsqf(d2[u]);
+        }
+        float pz[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) pz[u] = Z[j + u];
+        int_batch<A, SCALED>(r, pz, dmin, Sw, Swz);
+        j += B;
+    }
+    // fewer than 2B points in all: at most one whole batch, then the rest
     for (; j + B <= j1; j += B) {
-        float px[B], py[B], pz[B];
+        float r[B], pz[B];
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-            px[u] = X[j + u];
-            py[u] = Y[j + u];
+            r[u] = __builtin_amdgcn_rsqf(sqdist(qx, qy, X[j + u], Y[j + u]));
             pz[u] = Z[j + u];
         }
-        float w0 = weight(sqdist(qx, qy, px[0], py[0]));
-        float sw = w0, swz = w0 * pz[0];
-#pragma unroll
-        for (int u = 1; u < B; ++u) {
-            const float w = weight(sqdist(qx, qy, px[u], py[u]));
-            sw += w;
-            swz = fmaf(w, pz[u], swz);
-        }
-        Sw += (double)sw;
-        Swz += (double)swz;
+        int_batch<A, SCALED>(r, pz, dmin, Sw, Swz);
     }
     for (; j < j1; ++j) {
-        const float w = weight(sqdist(qx, qy, X[j], Y[j]));
+        const float r = __builtin_amdgcn_rsqf(sqdist(qx, qy, X[j], Y[j]));
+        const float w = ipow<A>(SCALED ? dmin * r : r);
         Sw += (double)w;
         Swz += (double)(w * Z[j]);
     }
@@ -305,10 +469,17 @@ __device__ __forceinline__ void scan_wsum_any(cptr X, cptr Y, cptr Z, int j0, in
     bool any_coincident = false;
 #pragma unroll
     for (int s = 0; s < Q; ++s) any_coincident |= coincident(aL0[s]);
-    if (__any(any_coincident))
-        scan_wsum<Q, true>(X, Y, Z, j0, j1, qx, qy, na, aL0, Sw, Swz);
-    else
-        scan_wsum<Q, false>(X, Y, Z, j0, j1, qx, qy, na, aL0, Sw, Swz);
+    if constexpr (Q == 1) {
+        if (__any(any_coincident))
+            scan_wsum1<true>(X, Y, Z, j0, j1, qx[0], qy[0], na[0], aL0[0], Sw[0], Swz[0]);
+        else
+            scan_wsum1<false>(X, Y, Z, j0, j1, qx[0], qy[0], na[0], aL0[0], Sw[0], Swz[0]);
+    } else {
+        if (__any(any_coincident))
+            scan_wsum<Q, true>(X, Y, Z, j0, j1, qx, qy, na, aL0, Sw, Swz);
+        else
+            scan_wsum<Q, false>(X, Y, Z, j0, j1, qx, qy, na, aL0, Sw, Swz);
+    }
 }
 
 template <int Q>
