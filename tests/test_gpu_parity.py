@@ -216,6 +216,23 @@ def test_other_alpha_levels(ctx, torch, dtype, levels):
         assert rel_err(out, idw, scale).max() <= (TOL_F64 if dtype == np.float64 else TOL_F32)
 
 
+# m around multiples of the 16-point pass-2 batch: the software-pipelined
+# loops need two whole batches, end on the last whole one and leave the rest
+# to the point-by-point tail; whole levels take the rsq loop, the others the
+# log2/exp2 loop, and queries on data points its clamped variant
+@pytest.mark.parametrize("m", [31, 32, 33, 47, 48, 49, 64, 95])
+@pytest.mark.parametrize("levels", [(5, 5, 5, 5, 5), (0.5, 1.5, 2.5, 4, 6)])
+@pytest.mark.parametrize("on_point", [0.0, 0.05])
+def test_pass2_batch_boundaries(ctx, torch, m, levels, on_point):
+    inst = workloads.clustered(m=m, n=300, seed=40 + m, k=min(8, m), on_point=on_point)
+    inst.levels = levels
+    out = gpu_run(ctx, torch, inst)
+    o, scale = ref(inst)
+    err = rel_err(out, o, scale).max()
+    say("m=%d levels=%s on_point=%g: max err %.3e" % (m, levels, on_point, err))
+    assert err <= TOL_F32
+
+
 def test_empty_query_set_is_a_no_op(ctx, torch):
     d = torch.rand(2, 10, device="cuda")
     z = torch.rand(10, device="cuda")
