@@ -231,7 +231,11 @@ def main():
             "value": 2.0 * inst.m * len(idx) / dt, "unit": "pair-evals/s", "cores": cores,
             "kind": "oracle",
             "sample": "first %d queries of the workload against all %d data points (%.1f s)"
-                      % (len(idx), inst.m, dt)}
+                      % (len(idx), inst.m, dt),
+            # the whole step at the sampled rate (the oracle's cost per query
+            # does not depend on the query)
+            "full_step_s_extrapolated": 2.0 * inst.m * inst.n / (2.0 * inst.m * len(idx) / dt),
+            "gpu_speedup": (2.0 * inst.m * inst.n / (ms * 1e-3)) / (2.0 * inst.m * len(idx) / dt)}
 
     ctx.close()
     print(json.dumps(result), flush=True)
