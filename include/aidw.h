@@ -216,7 +216,7 @@ aidw_status aidw_tune_load(aidw_t h, const char* path);
  * Not part of the method: a measurement of the device that bounds the FP32
  * kernels.  Their time is set by how long the instructions occupy a SIMD,
  * and without packed FP32 (disabled in every kernel of this library) that
- * is not what the 157.3 TFLOP/s packed-FMA figure assumes.  Runs three short
+ * is not what the 157.3 TFLOP/s packed-FMA figure assumes.  Runs five short
  * probe kernels (about 0.1 s) on the handle's stream; each value is SIMD
  * cycles per wave64 instruction. */
 typedef struct aidw_issue_costs {
@@ -225,6 +225,11 @@ typedef struct aidw_issue_costs {
     double exp_cycles_beside_fma;  /* v_exp_f32 when other waves of the SIMD run FMAs */
     double clock_ghz;              /* clock used for the conversion */
     int compute_units;
+    /* Two VALU instructions of different waves can issue in the same cycle
+     * unless both read an SGPR (a data point's coordinate, in these
+     * kernels): */
+    double sgpr_operand_cycles;      /* v_sub_f32 v, s, v only */
+    double sgpr_beside_vgpr_cycles;  /* the same alternating with VGPR-only multiplies */
 } aidw_issue_costs;
 
 aidw_status aidw_probe_issue_costs(aidw_t h, aidw_issue_costs* out);

@@ -45,7 +45,8 @@ class aidw_options(ctypes.Structure):
 class aidw_issue_costs(ctypes.Structure):
     _fields_ = [("fma_cycles", ctypes.c_double), ("exp_cycles", ctypes.c_double),
                 ("exp_cycles_beside_fma", ctypes.c_double), ("clock_ghz", ctypes.c_double),
-                ("compute_units", ctypes.c_int)]
+                ("compute_units", ctypes.c_int), ("sgpr_operand_cycles", ctypes.c_double),
+                ("sgpr_beside_vgpr_cycles", ctypes.c_double)]
 
 
 class aidw_problem(ctypes.Structure):

@@ -1,5 +1,6 @@
 // Issue-cost probe of libaidw (declared in include/aidw.h): how many SIMD
-// cycles a wave64 FP32 FMA and a v_exp_f32 occupy on this device, compiled
+// cycles a wave64 FP32 FMA, a v_exp_f32 and a VALU instruction with an SGPR
+// operand occupy on this device, compiled
 // like every kernel here (packed FP32 off).  These costs, not the packed-FMA
 // peak, bound the FP32-scaled kernels.
 //
@@ -7,7 +8,11 @@
 // workgroups per CU give 8 waves per SIMD.  Kinds:
 //   0: FMAs only (8 per chain per iteration);
 //   1: one exp2 (after one FMA) per chain per iteration;
-//   2: waves (w / 4) even run kind 1, odd run kind 0, so SIMDs hold both.
+//   2: waves (w / 4) even run kind 1, odd run kind 0, so SIMDs hold both;
+//   3: subtractions with an SGPR operand only (v_sub_f32 v, s, v);
+//   4: those alternating with VGPR-only multiplies.
+// Two VALU instructions of different waves can issue in one cycle unless
+// both read an SGPR: kinds 3 and 4 show the difference.
 #include <algorithm>
 
 #include "handle.h"
@@ -33,9 +38,19 @@ __global__ __launch_bounds__(kThreads) void issue_probe(float* __restrict__ out,
         b[j] = 0.5f + j * 1e-3f;
     }
     const bool exp_wave = KIND == 1 || (KIND == 2 && ((wave >> 2) & 1) == 0);
+    const float c = 0.999f + threadIdx.x * 1e-9f;  // per lane: a VGPR operand
     for (int i = 0; i < iters; ++i) {
         const float s = src[i & 63];
-        if (exp_wave) {
+        if constexpr (KIND >= 3) {
+            // s is wave-uniform (a scalar load), so it stays an SGPR operand
+#pragma unroll
+            for (int f = 0; f < kFmaPerIter; ++f)
+#pragma unroll
+                for (int j = 0; j < kChains; ++j) {
+                    b[j] = s - b[j];
+                    if (KIND == 4) a[j] = a[j] * c;
+                }
+        } else if (exp_wave) {
 #pragma unroll
             for (int j = 0; j < kChains; ++j) a[j] = __builtin_amdgcn_exp2f(fmaf(a[j], -1.0f, s));
         } else {
@@ -88,13 +103,15 @@ aidw_status aidw_probe_issue_costs(aidw_t h, aidw_issue_costs* out) {
     hipError_t e = hipMemsetAsync(src, 0, 64 * sizeof(float), h->stream);
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    double ms[3] = {0, 0, 0};
+    double ms[5] = {0, 0, 0, 0, 0};
     const int iters = 8192;
     // a first untimed round brings the clock up
     if (e == hipSuccess) e = time_probe<0>(h->stream, blocks, buf, src, iters, e0, e1, &ms[0]);
     if (e == hipSuccess) e = time_probe<0>(h->stream, blocks, buf, src, iters, e0, e1, &ms[0]);
     if (e == hipSuccess) e = time_probe<1>(h->stream, blocks, buf, src, iters, e0, e1, &ms[1]);
     if (e == hipSuccess) e = time_probe<2>(h->stream, blocks, buf, src, iters, e0, e1, &ms[2]);
+    if (e == hipSuccess) e = time_probe<3>(h->stream, blocks, buf, src, iters, e0, e1, &ms[3]);
+    if (e == hipSuccess) e = time_probe<4>(h->stream, blocks, buf, src, iters, e0, e1, &ms[4]);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     device_free(h, mem, bytes);
@@ -114,6 +131,9 @@ aidw_status aidw_probe_issue_costs(aidw_t h, aidw_issue_costs* out) {
     const double fma_side = waves_per_simd / 2 * kChains * kFmaPerIter * fma;
     const double exp_side_fma = waves_per_simd / 2 * kChains * fma;
     const double exp_beside = (total - fma_side - exp_side_fma) / (waves_per_simd / 2 * kChains);
+    const double per_inst = kChains * kFmaPerIter;
+    out->sgpr_operand_cycles = per_wave_iter(ms[3]) / per_inst;
+    out->sgpr_beside_vgpr_cycles = per_wave_iter(ms[4]) / (2 * per_inst);
     out->fma_cycles = fma;
     out->exp_cycles = exp_alone;
     out->exp_cycles_beside_fma = std::max(0.0, exp_beside);

@@ -476,6 +476,10 @@ def test_issue_cost_probe_is_plausible(ctx, torch):
     assert 1.5 < c["fma_cycles"] < 8.0
     assert c["fma_cycles"] < c["exp_cycles"] < 64.0
     assert 0.0 <= c["exp_cycles_beside_fma"] < 64.0
+    # an SGPR-operand instruction costs at least what a plain one does, and
+    # interleaving VGPR-only work can only lower the cost per instruction
+    assert c["fma_cycles"] * 0.8 < c["sgpr_operand_cycles"] < 16.0
+    assert 1.0 < c["sgpr_beside_vgpr_cycles"] <= c["sgpr_operand_cycles"] * 1.05
 
 
 # ---- size limits and malformed pointers (host validation, nothing launched) ----------
