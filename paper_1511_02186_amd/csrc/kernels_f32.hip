@@ -176,15 +176,20 @@ __device__ __forceinline__ void scan_wsum1(cptr X, cptr Y, cptr Z, int j0, int j
                                            double& Swz) {
     constexpr int B = batch2_for<1>();
     auto from_d2 = [&](const float (&d2)[B], float (&w)[B]) {
-        float l[B];
+        float t[B];
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int u = 0; u < B; ++u) l[u] = __builtin_amdgcn_logf(d2[u]);
+        for (int u = 0; u < B; ++u) t[u] = __builtin_amdgcn_logf(d2[u]);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-            float t = fmaf(na, l[u], aL0);
-            if (SAFE) t = fminf(t, 0.0f);
-            w[u] = __builtin_amdgcn_exp2f(t);
+            t[u] = fmaf(na, t[u], aL0);
+            if (SAFE) t[u] = fminf(t[u], 0.0f);
         }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < B; ++u) w[u] = __builtin_amdgcn_exp2f(t[u]);
+        __builtin_amdgcn_sched_barrier(0);
     };
     auto weights = [&](const float (&px)[B], const float (&py)[B], float (&w)[B]) {
         float d2[B];
