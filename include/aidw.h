@@ -88,7 +88,8 @@ typedef enum aidw_precision {
                                   still sums over all m points.  Not with knn_idx,
                                   FP32-scaled only.  Uses about 14 m + (16 + 16 S) n
                                   bytes of library workspace (S data segments of
-                                  pass 2, 1 unless there are few queries). */
+                                  pass 2: about one per 128 K data points, at most 8,
+                                  more when there are few queries). */
 
 typedef struct aidw_options {
     int device;                        /* HIP device ordinal */
