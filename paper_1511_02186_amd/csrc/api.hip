@@ -174,19 +174,22 @@ namespace aidw {
 namespace detail {
 
 // Number of data segments for an FP32-scaled problem.  1 (the fused kernel)
-// whenever the 64-query tiles alone fill at least half of 8 waves per SIMD:
-// the fused kernel overlaps one wave's pass 1 with another's pass 2, which
-// the split launches cannot.  Otherwise enough (tile, segment) waves for
-// about 8 per SIMD, with segments of at least kMinSegment points.
+// when the 64-query tiles alone give at least two rounds of 8 waves per
+// SIMD.  Below that the fused kernel leaves SIMDs short of waves to pair
+// instructions from (one round or less: 102 ms fused against 81 ms in 8
+// segments at m = 2^20, n = 2^18), so the problem runs as (tile, segment)
+// waves, about four rounds' worth, with segments of at least kMinSegment
+// points.  At two rounds the two are even (m = n = 2^20: 306 ms fused,
+// 300-306 ms in 2-8 segments), and the fused kernel needs no workspace.
 constexpr int kMinSegment = 2048;
 
 aidw::SplitPlan split_plan_for(const aidw_ctx* h, const aidw_tuning& t, int64_t m, int64_t n) {
     aidw::SplitPlan sp{1, (int)m, (int)((n + aidw::kWaveSize - 1) / aidw::kWaveSize)};
     int want = t.split_segments;
     if (want == 0) {
-        const int64_t target = (int64_t)(h->cu_count > 0 ? h->cu_count : 256) * 4 * 8;
-        if (2 * sp.tiles >= target) return sp;
-        want = (int)std::min<int64_t>((target + sp.tiles - 1) / sp.tiles, 1 << 20);
+        const int64_t round = (int64_t)(h->cu_count > 0 ? h->cu_count : 256) * 4 * 8;
+        if (sp.tiles >= 2 * round) return sp;
+        want = (int)std::min<int64_t>((4 * round + sp.tiles - 1) / sp.tiles, 1 << 20);
     }
     int64_t seg = (m + want - 1) / want;
     if (t.split_segments == 0) seg = std::max<int64_t>(seg, kMinSegment);
