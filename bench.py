@@ -94,6 +94,17 @@ def parse():
     return ap.parse_args()
 
 
+def step_kernels(torch, inst):
+    """The kernels one step runs: the fused kernel while the 64-query tiles
+    give two rounds of 8 waves per SIMD, else the split-m launches (the
+    library's automatic plan)."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    tiles = (inst.n + 63) // 64
+    if tiles >= 2 * cus * 4 * 8:
+        return "aidw_f32_fused"
+    return "aidw_f32_knn_part + aidw_f32_knn_merge + aidw_f32_wsum_part + aidw_f32_wsum_reduce"
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -165,7 +176,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": measured_traffic() if inst.m == inst.n == 1 << 20 else None,
-                     "kernel": "aidw_f32_fused", "flop_per_pair_eval": FLOP_PER_PAIR},
+                     "kernel": step_kernels(torch, inst), "flop_per_pair_eval": FLOP_PER_PAIR},
         "step_ms": {"p10": float(np.percentile(per, 10)), "p50": float(np.median(per)),
                     "p90": float(np.percentile(per, 90)), "wall_s": wall},
     }
