@@ -187,8 +187,9 @@ typedef struct aidw_tuning {
     int max_waves_per_simd;  /* cap on resident waves per SIMD (1..8), enforced by
                                 reserving LDS per workgroup */
     int split_segments;      /* split the m data points into this many segments
-                                processed in parallel (1: never split); for
-                                problems with too few queries to fill the GPU */
+                                processed in parallel (1: never split); chosen
+                                automatically when the 64-query tiles give fewer
+                                than two rounds of 8 waves per SIMD */
 } aidw_tuning;
 
 /* Fix the launch shape used for FP32-scaled problems (NULL restores the
