@@ -426,21 +426,24 @@ class Context:
         return p
 
     def interpolate(self, data_xy, data_z, query_xy, k, alpha_levels=(1, 2, 3, 4, 5),
-                    R_min=0.0, R_max=2.0, area=None, diag=False, flags=0, out=None):
+                    R_min=0.0, R_max=2.0, area=None, diag=False, flags=0, out=None, knn=True):
         """AIDW of the queries over the data (torch tensors on the GPU).
 
-        Returns `out`, or (out, r_obs, alpha, knn_idx) with diag=True."""
+        Returns `out`, or (out, r_obs, alpha, knn_idx) with diag=True; knn=False
+        leaves knn_idx None (asking for the indices keeps m unsplit)."""
         import torch
 
         n = query_xy.shape[-1]
         dev = data_xy.device
         if out is None:
             out = torch.empty(n, dtype=data_xy.dtype, device=dev)
+        want_knn = knn
         r_obs = alpha = knn = None
         if diag:
             r_obs = torch.empty(n, dtype=torch.float64, device=dev)
             alpha = torch.empty(n, dtype=torch.float64, device=dev)
-            knn = torch.empty((n, int(k)), dtype=torch.int32, device=dev)
+            if want_knn:
+                knn = torch.empty((n, int(k)), dtype=torch.int32, device=dev)
         self.bind_current_stream()
         p = self.problem(data_xy, data_z, query_xy, k, out, alpha_levels, R_min, R_max, area,
                          r_obs, alpha, knn, flags)

@@ -185,12 +185,13 @@ def _run(ctx, torch, inst, segments=0, diag=False):
     data_xy, data_z, query_xy = aidw.to_device(inst)
     ctx.set_tuning(split_segments=segments)
     try:
+        # no knn_idx: asking for the indices would keep m unsplit
         r = ctx.interpolate(data_xy, data_z, query_xy, inst.k, inst.levels, inst.R_min,
-                            inst.R_max, inst.area, diag=diag)
+                            inst.R_max, inst.area, diag=diag, knn=False)
     finally:
         ctx.set_tuning()
     torch.cuda.synchronize()
-    return tuple(t.cpu().numpy() for t in r) if diag else r.cpu().numpy()
+    return tuple(None if t is None else t.cpu().numpy() for t in r) if diag else r.cpu().numpy()
 
 
 @pytest.mark.parametrize("segments", [2, 7, 64, 1000])
@@ -214,6 +215,30 @@ def test_automatic_split_for_few_queries(ctx, torch, m, n):
     idx = np.unique(np.linspace(0, n - 1, min(n, 24)).astype(int))
     o, scale = ref(inst, idx)
     assert rel_err(out[idx], o, scale).max() <= TOL_F32
+
+
+def test_automatic_split_boundary_two_rounds(ctx, torch):
+    """The automatic plan keeps the fused kernel from two rounds of 64-query
+    tiles (8 waves per SIMD) up and splits m one tile below.  The same
+    queries, run both ways: identical k-nearest statistics, outputs equal to
+    FP64 summation order, and both within the bar on sampled queries."""
+    import copy
+
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    n = 2 * cus * 4 * 8 * 64
+    inst = workloads.paper_scale(m=1 << 16, n=n, seed=77, k=15)
+    below = copy.copy(inst)
+    below.query_x = np.ascontiguousarray(inst.query_x[: n - 64])
+    below.query_y = np.ascontiguousarray(inst.query_y[: n - 64])
+    whole, r0, a0, _ = _run(ctx, torch, inst, diag=True)
+    split, r1, a1, _ = _run(ctx, torch, below, diag=True)
+    assert np.array_equal(r0[: n - 64], r1)
+    assert np.array_equal(a0[: n - 64], a1)
+    assert np.allclose(split, whole[: n - 64], rtol=2e-7, atol=0)
+    idx = np.unique(np.linspace(0, n - 65, 48).astype(int))
+    o, scale = ref(inst, idx)
+    assert rel_err(whole[idx], o, scale).max() <= TOL_F32
+    assert rel_err(split[idx], o, scale).max() <= TOL_F32
 
 
 def test_split_with_alpha_zero_and_coincident_queries(ctx, torch):
