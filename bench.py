@@ -383,7 +383,7 @@ def _serving_data(torch, spec, gen):
     return xy.contiguous(), torch.exp(-10.0 * d2).sum(-1).contiguous()
 
 
-def bench_serving(ctx, torch, aidw, workloads, count, rate=2000.0, seed=4):
+def bench_serving(ctx, torch, aidw, workloads, count, rate=2000.0, seed=4, check_jobs=0):
     """Poisson arrivals of jobs with m log-uniform in [4096, 2^20] and n
     log-uniform in [256, 2^18], uniform or clustered points; data sets used
     by more than one request are registered once (library-owned, resident),
@@ -420,8 +420,8 @@ def bench_serving(ctx, torch, aidw, workloads, count, rate=2000.0, seed=4):
             delay = r.t_arrival - (time.perf_counter() - t0)
             if delay > 0:
                 time.sleep(delay)
-            tickets.append(aidw.aidw_submit(srv, spec))
-        res = [aidw.aidw_wait(srv, t, 600.0) for t in tickets]
+            tickets.append(aidw.aidw_server_submit(srv, spec))
+        res = [aidw.aidw_server_wait(srv, t, 600.0) for t in tickets]
         wall = time.perf_counter() - t0
         _, stats = aidw.aidw_server_stats(srv)
     finally:
@@ -429,6 +429,7 @@ def bench_serving(ctx, torch, aidw, workloads, count, rate=2000.0, seed=4):
         for d in ids.values():
             aidw.aidw_dataset_release(ctx.h, d)
     ok = sum(1 for st, js, _ in res if st == aidw.AIDW_OK and js == aidw.AIDW_OK)
+    err, checked = serving_error(torch, reqs, jobs, data, check_jobs)
     lat = np.array([l for _, _, l in res]) * 1e3
     pairs = float(sum(2.0 * specs[r.dataset][0] * r.n for r in reqs))
     span = reqs[-1].t_arrival
@@ -439,7 +440,31 @@ def bench_serving(ctx, torch, aidw, workloads, count, rate=2000.0, seed=4):
             "wall_s": wall,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "pair_evals_per_s": pairs / wall, "offered_pair_evals_per_s": pairs / span,
-            "ticks": stats["ticks"]}
+            "ticks": stats["ticks"], "max_rel_err_vs_oracle": err,
+            "checked": "%d queries of %d jobs spread over the run" % checked}
+
+
+def serving_error(torch, reqs, jobs, data, check_jobs, per_job=2):
+    """Max relative error against the FP64 oracle over `per_job` queries of
+    `check_jobs` jobs spread evenly over the run."""
+    import oracle
+
+    if check_jobs <= 0:
+        return None, (0, 0)
+    worst, nq = 0.0, 0
+    picks = np.unique(np.linspace(0, len(reqs) - 1, min(check_jobs, len(reqs))).astype(int))
+    for i in picks:
+        r = reqs[i]
+        q, out, _ = jobs[i]
+        xy, z = (t.cpu().numpy() for t in data[r.dataset])
+        idx = np.unique(np.linspace(0, r.n - 1, per_job).astype(int))
+        Q = q.cpu().numpy()[:, idx]
+        want = oracle.run(xy[0], xy[1], z, Q[0], Q[1], r.k, area=1.0)
+        scale = oracle.run(xy[0], xy[1], np.abs(z), Q[0], Q[1], r.k, area=1.0)
+        got = out.cpu().numpy()[idx].astype(np.float64)
+        worst = max(worst, float(np.max(np.abs(got - want) / scale)))
+        nq += len(idx)
+    return worst, (nq, len(picks))
 
 
 def bench_serving_all(torch, aidw, workloads, count, sweep_count):
@@ -447,7 +472,7 @@ def bench_serving_all(torch, aidw, workloads, count, sweep_count):
     curve, on a handle with a 64 GB HBM budget."""
     ctx = aidw.Context(0, hbm_budget_bytes=64 << 30)
     try:
-        res = bench_serving(ctx, torch, aidw, workloads, count)
+        res = bench_serving(ctx, torch, aidw, workloads, count, check_jobs=50)
         sweep = []
         for rate in (250.0, 500.0, 1000.0):
             r = bench_serving(ctx, torch, aidw, workloads, sweep_count, rate=rate, seed=40)

@@ -21,7 +21,7 @@
  *    retains them past the call (or, for asynchronous calls, past the work's
  *    completion on the handle's stream).
  *  - Arguments are validated on the host before any device work.  On error
- *    nothing is launched, `out` is left untouched, and aidw_last_error()
+ *    nothing is launched, `out` is left untouched, and aidw_last_error(h)
  *    returns a message for the calling thread.
  *  - n == 0 is a valid no-op.
  *  - Work is issued on the handle's stream (aidw_set_stream; the NULL stream
@@ -50,10 +50,15 @@ extern "C" {
 #endif
 
 #define AIDW_VERSION_MAJOR 0
-#define AIDW_VERSION_MINOR 1
+#define AIDW_VERSION_MINOR 2
 
 /* Largest supported k (neighbours kept in registers per query). */
 #define AIDW_KMAX 32
+
+/* Largest number of data points m, and of queries n, of one problem:
+ * 2^31 - 2^16, so that every point index and every scan bound the kernels
+ * form stays inside 32-bit signed arithmetic. */
+#define AIDW_MAX_POINTS 2147418112LL
 
 typedef enum aidw_status {
     AIDW_OK = 0,
@@ -99,6 +104,16 @@ typedef struct aidw_options {
                                           aidw_tune_save, loaded at creation (a
                                           missing file is ignored, an invalid one
                                           fails creation with AIDW_EINVAL) */
+    int deterministic;                 /* Every path of the library is deterministic run
+                                          to run (no floating-point atomics; every sum
+                                          has a fixed order).  Nonzero additionally makes
+                                          FP32-scaled results independent of the
+                                          automatic launch-shape choices, which depend on
+                                          the device's compute-unit count and on tuning
+                                          tables: such problems then always run the
+                                          unsplit one-query-per-lane kernel (the kernel
+                                          batched launches use), and grid-mode pass 2
+                                          splits the data by m alone. */
 } aidw_options;
 
 typedef struct aidw_ctx* aidw_t;
@@ -108,9 +123,9 @@ typedef struct aidw_problem {
     aidw_precision precision;
     const void* data_xy;     /* [2][m] planar x row then y row */
     const void* data_z;      /* [m] */
-    int64_t m;               /* data points, 1 <= m <= 2^31 - 1 */
+    int64_t m;               /* data points, 1 <= m <= AIDW_MAX_POINTS */
     const void* query_xy;    /* [2][n] planar */
-    int64_t n;               /* queries, 0 <= n <= 2^31 - 1 */
+    int64_t n;               /* queries, 0 <= n <= AIDW_MAX_POINTS */
     int k;                   /* neighbours for r_obs (Eq. 3), 1 <= k <= min(m, AIDW_KMAX) */
     double alpha_levels[5];  /* alpha_1..alpha_5 of Eq. 6; finite, >= 0 */
     double R_min, R_max;     /* Eq. 5 bounds; R_max > R_min, R_max > 0 */
@@ -124,12 +139,13 @@ typedef struct aidw_problem {
 } aidw_problem;
 
 /* Create a handle on opt->device (opt may be NULL: device 0, FP32-scaled,
- * no budget).  Returns AIDW_EINVAL for a bad device, AIDW_EDEVICE if HIP
+ * no budget, not deterministic).  Returns AIDW_EINVAL for a bad device, AIDW_EDEVICE if HIP
  * cannot be initialised. */
 aidw_status aidw_create(aidw_t* out, const aidw_options* opt);
 
-/* Wait for the handle's outstanding work, free library-owned memory and the
- * handle.  NULL is ignored. */
+/* Finish the jobs submitted to the handle's serving loop, wait for the
+ * handle's outstanding work, free library-owned memory and the handle.  NULL
+ * is ignored. */
 void aidw_destroy(aidw_t h);
 
 /* Issue subsequent work on `stream` (a hipStream_t of the handle's device,
@@ -265,19 +281,27 @@ aidw_status aidw_interpolate_batch(aidw_t h, const aidw_problem* problems, int c
 
 /* ---- Serving: continuous batching of submitted jobs -----------------------
  * A server owns a worker thread, `streams` HIP streams and a device arena.
- * Submitted jobs are admitted first-in first-out while the arena has room
- * for their workspace (jobs whose data set exceeds `segment_points` points
- * are split into data segments and need a workspace; the others need none).
- * Each scheduling tick packs work items of all admitted jobs -- jobs that
- * waited longer than max_wait_s first, then the shortest remaining work --
- * into one launch of about tick_pair_evals distance evaluations, and up to
- * `streams` ticks run at once, so jobs that arrive while others are on the
- * GPU start with the next tick.  A job's result does not depend on which
- * other jobs it shares ticks with.  All jobs are FP32-scaled. */
+ * Submitted jobs are admitted in arrival order while the arena has room for
+ * their workspace (FP32-scaled jobs whose data set exceeds `segment_points`
+ * points are split into data segments and need a workspace; the others need
+ * none).  A job that does not fit does not hold back later jobs that need no
+ * workspace; later jobs that need workspace pass it only until it has waited
+ * max_wait_s.  Each scheduling tick packs work items of all admitted jobs --
+ * jobs that waited longer than max_wait_s first, then the shortest remaining
+ * work -- into about tick_pair_evals distance evaluations (FP64 jobs counted
+ * at 20 times their pair count, their relative cost), launched on one
+ * stream, and up to `streams` ticks run at once, so jobs that arrive while
+ * others are on the GPU start with the next tick.  A job's result does not
+ * depend on which other jobs it shares ticks with.
+ *
+ * Each handle has a serving loop of its own, created with default options by
+ * its first aidw_submit / aidw_submit_batch and finished by aidw_destroy;
+ * aidw_server_create makes further servers with explicit options. */
 
 /* A data set copied into library-owned device memory (counted against the
  * handle's budget).  data_xy [2][m] and data_z [m] are float device
- * pointers; the copy is complete when the call returns. */
+ * pointers; the copy is complete when the call returns.  Registered data
+ * sets serve FP32-scaled jobs. */
 aidw_status aidw_dataset_register(aidw_t h, const void* data_xy, const void* data_z, int64_t m,
                                   double area, uint64_t* id);
 /* Free a registered data set.  AIDW_EAGAIN while unfinished jobs read it,
@@ -301,10 +325,13 @@ aidw_status aidw_server_create(aidw_t h, const aidw_server_options* opt, aidw_se
 /* Finish every submitted job, then stop the worker and free the server. */
 void aidw_server_destroy(aidw_server_t s);
 
-/* One job.  Pointers are float device pointers that must stay valid (and
- * the inputs unchanged) until the job is reported done. */
+/* One job (Eq. 1-6 for n queries over m data points, as aidw_problem).
+ * Pointers are device pointers (float for AIDW_FP32_SCALED, double for
+ * AIDW_FP64) that must stay valid, and the inputs unchanged, until the job
+ * is reported done. */
 typedef struct aidw_job {
-    uint64_t dataset;        /* a registered data set, or 0 to use the next four fields */
+    uint64_t dataset;        /* a registered data set (FP32-scaled jobs only), or 0 to
+                                use the next four fields */
     const void* data_xy;     /* [2][m] */
     const void* data_z;      /* [m] */
     int64_t m;
@@ -314,32 +341,46 @@ typedef struct aidw_job {
     int k;
     double alpha_levels[5];
     double R_min, R_max;
-    void* out;               /* [n] float */
+    aidw_precision precision; /* AIDW_FP32_SCALED or AIDW_FP64 (the plain FP64 kernel;
+                                 never split into data segments) */
+    void* out;               /* [n] */
     double* r_obs;           /* optional [n] */
     double* alpha;           /* optional [n] */
+    int32_t* knn_idx;        /* optional [n][k], sorted by (distance, index); an
+                                FP32-scaled job that asks for it is not split */
 } aidw_job;
 
-/* Validate and enqueue a job; *ticket identifies it.  Thread-safe.  A job
- * whose workspace can never fit the arena is accepted and reported as
- * failed with AIDW_ENOMEM by aidw_poll. */
-aidw_status aidw_submit(aidw_server_t s, const aidw_job* job, uint64_t* ticket);
+/* Validate and enqueue a job on the server; *ticket identifies it.
+ * Thread-safe.  A job whose workspace can never fit the arena is accepted
+ * and reported as failed with AIDW_ENOMEM by aidw_server_poll. */
+aidw_status aidw_server_submit(aidw_server_t s, const aidw_job* job, uint64_t* ticket);
 /* Validate and enqueue `count` jobs at once (host array jobs[count]);
  * tickets[i] identifies jobs[i].  All or nothing: if any job is invalid (the
  * error names its index) or names an unknown data set, none is enqueued and
  * every ticket is 0.  Jobs submitted together reach the scheduler together,
  * so they share ticks as far as the arena and the tick quota allow.
  * Thread-safe. */
-aidw_status aidw_submit_batch(aidw_server_t s, const aidw_job* jobs, int count,
-                              uint64_t* tickets);
+aidw_status aidw_server_submit_batch(aidw_server_t s, const aidw_job* jobs, int count,
+                                     uint64_t* tickets);
 /* AIDW_EAGAIN while the job is queued or running.  Once it has finished,
  * returns AIDW_OK with *job_status (AIDW_OK or the job's error) and
  * *latency_s (seconds from submission to completion), then forgets the
- * ticket (later polls: AIDW_ENOTFOUND).  Thread-safe. */
-aidw_status aidw_poll(aidw_server_t s, uint64_t ticket, aidw_status* job_status,
-                      double* latency_s);
-/* aidw_poll until the job finishes or timeout_s passes (AIDW_EAGAIN);
+ * ticket (later polls: AIDW_ENOTFOUND).  A failed job is reported only once
+ * no kernel touches its buffers.  Thread-safe. */
+aidw_status aidw_server_poll(aidw_server_t s, uint64_t ticket, aidw_status* job_status,
+                             double* latency_s);
+/* aidw_server_poll until the job finishes or timeout_s passes (AIDW_EAGAIN);
  * timeout_s < 0 waits indefinitely. */
-aidw_status aidw_wait(aidw_server_t s, uint64_t ticket, double timeout_s, aidw_status* job_status,
+aidw_status aidw_server_wait(aidw_server_t s, uint64_t ticket, double timeout_s,
+                             aidw_status* job_status, double* latency_s);
+
+/* The same four calls on the handle's own serving loop (created on first
+ * use with default server options; its arena counts against the handle's
+ * budget).  Tickets of different servers are unrelated. */
+aidw_status aidw_submit(aidw_t h, const aidw_job* job, uint64_t* ticket);
+aidw_status aidw_submit_batch(aidw_t h, const aidw_job* jobs, int count, uint64_t* tickets);
+aidw_status aidw_poll(aidw_t h, uint64_t ticket, aidw_status* job_status, double* latency_s);
+aidw_status aidw_wait(aidw_t h, uint64_t ticket, double timeout_s, aidw_status* job_status,
                       double* latency_s);
 
 typedef struct aidw_server_counters {
@@ -356,8 +397,12 @@ aidw_status aidw_server_stats(aidw_server_t s, aidw_server_counters* out);
 /* Wait until all work issued on the handle's stream has finished. */
 aidw_status aidw_synchronize(aidw_t h);
 
-/* Message describing the calling thread's most recent error ("" if none). */
-const char* aidw_last_error(void);
+/* Message describing the calling thread's most recent failed call on handle
+ * h (calls on its batches and servers included), or, with h == NULL, the
+ * calling thread's most recent failed call of any kind (aidw_create
+ * included).  "" if there is none.  The string stays valid until the calling
+ * thread's next call into the library. */
+const char* aidw_last_error(aidw_t h);
 
 /* Static name of a status code. */
 const char* aidw_status_string(aidw_status s);

@@ -35,11 +35,13 @@ AIDW_ACCESS_NAIVE = 2
 AIDW_LAYOUT_SOA = 0
 AIDW_LAYOUT_AOAS = 1
 AIDW_KMAX = 32
+AIDW_MAX_POINTS = (1 << 31) - (1 << 16)
 
 
 class aidw_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("default_precision", ctypes.c_int),
-                ("hbm_budget_bytes", ctypes.c_size_t), ("tune_path", ctypes.c_char_p)]
+                ("hbm_budget_bytes", ctypes.c_size_t), ("tune_path", ctypes.c_char_p),
+                ("deterministic", ctypes.c_int)]
 
 
 class aidw_issue_costs(ctypes.Structure):
@@ -94,9 +96,11 @@ class aidw_job(ctypes.Structure):
         ("alpha_levels", ctypes.c_double * 5),
         ("R_min", ctypes.c_double),
         ("R_max", ctypes.c_double),
+        ("precision", ctypes.c_int),
         ("out", ctypes.c_void_p),
         ("r_obs", ctypes.c_void_p),
         ("alpha", ctypes.c_void_p),
+        ("knn_idx", ctypes.c_void_p),
     ]
 
 
@@ -147,9 +151,19 @@ _SIGNATURES = {
     "aidw_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_server_options),
                                           ctypes.POINTER(ctypes.c_void_p)]),
     "aidw_server_destroy": (None, [ctypes.c_void_p]),
+    "aidw_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_job),
+                                          ctypes.POINTER(ctypes.c_uint64)]),
+    "aidw_probe_issue_costs": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_issue_costs)]),
+    "aidw_server_submit_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_job),
+                                                ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]),
+    "aidw_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64,
+                                        ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_double)]),
+    "aidw_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double,
+                                        ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_double)]),
     "aidw_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_job),
                                    ctypes.POINTER(ctypes.c_uint64)]),
-    "aidw_probe_issue_costs": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_issue_costs)]),
     "aidw_submit_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_job), ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_uint64)]),
     "aidw_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
@@ -157,7 +171,7 @@ _SIGNATURES = {
     "aidw_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double,
                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
     "aidw_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_server_counters)]),
-    "aidw_last_error": (ctypes.c_char_p, []),
+    "aidw_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "aidw_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "aidw_version": (ctypes.c_int, []),
 }
@@ -182,8 +196,10 @@ def status_name(status: int) -> str:
     return lib().aidw_status_string(int(status)).decode()
 
 
-def last_error() -> str:
-    return lib().aidw_last_error().decode()
+def last_error(h=None) -> str:
+    """The calling thread's most recent error message: of any call, or of
+    calls on handle h."""
+    return lib().aidw_last_error(h).decode()
 
 
 def check(status: int) -> int:
@@ -195,10 +211,10 @@ def check(status: int) -> int:
 # ---- the C entry points, same names ---------------------------------------
 
 def aidw_create(device: int = 0, default_precision: int = AIDW_FP32_SCALED,
-                hbm_budget_bytes: int = 0, tune_path=None) -> int:
+                hbm_budget_bytes: int = 0, tune_path=None, deterministic: int = 0) -> int:
     h = ctypes.c_void_p()
     opt = aidw_options(device, default_precision, hbm_budget_bytes,
-                       None if tune_path is None else os.fsencode(tune_path))
+                       None if tune_path is None else os.fsencode(tune_path), int(deterministic))
     check(lib().aidw_create(ctypes.byref(h), ctypes.byref(opt)))
     return h.value
 
@@ -310,9 +326,16 @@ def aidw_server_destroy(s) -> None:
     lib().aidw_server_destroy(s)
 
 
-def aidw_submit(s, job: aidw_job) -> int:
+def aidw_server_submit(s, job: aidw_job) -> int:
     t = ctypes.c_uint64()
-    check(lib().aidw_submit(s, ctypes.byref(job), ctypes.byref(t)))
+    check(lib().aidw_server_submit(s, ctypes.byref(job), ctypes.byref(t)))
+    return t.value
+
+
+def aidw_submit(h, job: aidw_job) -> int:
+    """Submit to the handle's own serving loop; returns the ticket."""
+    t = ctypes.c_uint64()
+    check(lib().aidw_submit(h, ctypes.byref(job), ctypes.byref(t)))
     return t.value
 
 
@@ -323,25 +346,47 @@ def aidw_probe_issue_costs(h):
     return {f: getattr(c, f) for f, _ in c._fields_}
 
 
-def aidw_submit_batch(s, jobs):
-    """Tickets of the jobs, submitted all or none (raises AidwError)."""
+def _tickets(fn, s, jobs):
     n = len(jobs)
     arr = (aidw_job * max(n, 1))(*jobs)
     tickets = (ctypes.c_uint64 * max(n, 1))()
-    check(lib().aidw_submit_batch(s, arr, n, tickets))
+    check(fn(s, arr, n, tickets))
     return [tickets[i] for i in range(n)]
 
 
-def aidw_poll(s, ticket):
+def aidw_server_submit_batch(s, jobs):
+    """Tickets of the jobs, submitted all or none (raises AidwError)."""
+    return _tickets(lib().aidw_server_submit_batch, s, jobs)
+
+
+def aidw_submit_batch(h, jobs):
+    """The same on the handle's own serving loop."""
+    return _tickets(lib().aidw_submit_batch, h, jobs)
+
+
+def aidw_server_poll(s, ticket):
     """(status, job_status, latency_s); status AIDW_EAGAIN while pending."""
     js, lat = ctypes.c_int(), ctypes.c_double()
-    st = lib().aidw_poll(s, int(ticket), ctypes.byref(js), ctypes.byref(lat))
+    st = lib().aidw_server_poll(s, int(ticket), ctypes.byref(js), ctypes.byref(lat))
     return st, js.value, lat.value
 
 
-def aidw_wait(s, ticket, timeout_s=-1.0):
+def aidw_poll(h, ticket):
     js, lat = ctypes.c_int(), ctypes.c_double()
-    st = lib().aidw_wait(s, int(ticket), float(timeout_s), ctypes.byref(js), ctypes.byref(lat))
+    st = lib().aidw_poll(h, int(ticket), ctypes.byref(js), ctypes.byref(lat))
+    return st, js.value, lat.value
+
+
+def aidw_server_wait(s, ticket, timeout_s=-1.0):
+    js, lat = ctypes.c_int(), ctypes.c_double()
+    st = lib().aidw_server_wait(s, int(ticket), float(timeout_s), ctypes.byref(js),
+                                ctypes.byref(lat))
+    return st, js.value, lat.value
+
+
+def aidw_wait(h, ticket, timeout_s=-1.0):
+    js, lat = ctypes.c_int(), ctypes.c_double()
+    st = lib().aidw_wait(h, int(ticket), float(timeout_s), ctypes.byref(js), ctypes.byref(lat))
     return st, js.value, lat.value
 
 
@@ -357,9 +402,10 @@ class Context:
     """Owns one aidw handle bound to a device and torch's current stream."""
 
     def __init__(self, device: int = 0, default_precision: int = AIDW_FP32_SCALED,
-                 hbm_budget_bytes: int = 0, tune_path=None):
+                 hbm_budget_bytes: int = 0, tune_path=None, deterministic: int = 0):
         self.device = device
-        self.h = aidw_create(device, default_precision, hbm_budget_bytes, tune_path)
+        self.h = aidw_create(device, default_precision, hbm_budget_bytes, tune_path,
+                             deterministic)
 
     def close(self):
         if self.h:
@@ -454,9 +500,13 @@ class Context:
 
 
 def make_job(query_xy, k, out, alpha_levels=(1, 2, 3, 4, 5), R_min=0.0, R_max=2.0,
-             dataset=0, data_xy=None, data_z=None, area=None, r_obs=None, alpha=None):
-    """aidw_job over torch tensors (float32, on the GPU): a registered dataset
-    id, or data_xy/data_z/area."""
+             dataset=0, data_xy=None, data_z=None, area=None, r_obs=None, alpha=None,
+             knn_idx=None):
+    """aidw_job over torch tensors on the GPU: a registered dataset id, or
+    data_xy/data_z/area.  float32 tensors give an FP32-scaled job, float64
+    tensors an FP64 one."""
+    import torch
+
     j = aidw_job()
     j.dataset = int(dataset)
     if not dataset:
@@ -466,6 +516,10 @@ def make_job(query_xy, k, out, alpha_levels=(1, 2, 3, 4, 5), R_min=0.0, R_max=2.
         j.data_z = data_z.data_ptr()
         j.m = data_z.numel()
         j.area = float(area)
+    prec = {torch.float32: AIDW_FP32_SCALED, torch.float64: AIDW_FP64}.get(out.dtype)
+    if prec is None:
+        raise TypeError("out must be float32 or float64, got %s" % out.dtype)
+    j.precision = prec
     j.query_xy = query_xy.data_ptr()
     j.n = out.numel()
     j.k = int(k)
@@ -474,6 +528,7 @@ def make_job(query_xy, k, out, alpha_levels=(1, 2, 3, 4, 5), R_min=0.0, R_max=2.
     j.out = out.data_ptr()
     j.r_obs = r_obs.data_ptr() if r_obs is not None else None
     j.alpha = alpha.data_ptr() if alpha is not None else None
+    j.knn_idx = knn_idx.data_ptr() if knn_idx is not None else None
     return j
 
 

@@ -9,13 +9,18 @@
 #include <vector>
 #include <new>
 #include <string>
+#include <unordered_map>
 
 #include "../../include/aidw.h"
 #include "common.h"
 #include "handle.h"
 
 namespace {
+// Messages of the calling thread: its most recent error of any call, and its
+// most recent error per handle.
 thread_local std::string g_last_error;
+thread_local std::unordered_map<const aidw_ctx*, std::string> g_handle_error;
+thread_local const aidw_ctx* g_scope = nullptr;
 }  // namespace
 
 namespace aidw {
@@ -28,8 +33,16 @@ aidw_status fail(aidw_status s, const char* fmt, ...) {
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     g_last_error = buf;
+    if (g_scope) g_handle_error[g_scope] = buf;
     return s;
 }
+
+ErrorScope::ErrorScope(const aidw_ctx* h) : prev_(g_scope) {
+    if (h) g_scope = h;
+}
+ErrorScope::~ErrorScope() { g_scope = prev_; }
+
+void forget_errors(const aidw_ctx* h) { g_handle_error.erase(h); }
 
 aidw_status hip_fail(hipError_t e, const char* what) {
     return fail(AIDW_EDEVICE, "%s: %s", what, hipGetErrorString(e));
@@ -72,8 +85,12 @@ aidw_status validate(const aidw_problem* p) {
     if (!p) return fail(AIDW_EINVAL, "problem is NULL");
     if (p->precision != AIDW_FP32_SCALED && p->precision != AIDW_FP64)
         return fail(AIDW_EINVAL, "unknown precision %d", (int)p->precision);
-    if (p->m < 1 || p->m > INT32_MAX) return fail(AIDW_EINVAL, "m = %lld out of [1, 2^31-1]", (long long)p->m);
-    if (p->n < 0 || p->n > INT32_MAX) return fail(AIDW_EINVAL, "n = %lld out of [0, 2^31-1]", (long long)p->n);
+    if (p->m < 1 || p->m > AIDW_MAX_POINTS)
+        return fail(AIDW_EINVAL, "m = %lld out of [1, %lld]", (long long)p->m,
+                    (long long)AIDW_MAX_POINTS);
+    if (p->n < 0 || p->n > AIDW_MAX_POINTS)
+        return fail(AIDW_EINVAL, "n = %lld out of [0, %lld]", (long long)p->n,
+                    (long long)AIDW_MAX_POINTS);
     if (p->k < 1 || p->k > AIDW_KMAX || (int64_t)p->k > p->m)
         return fail(AIDW_EINVAL, "k = %d out of [1, min(m, %d)]", p->k, AIDW_KMAX);
     if (!finite(p->area) || p->area <= 0.0) return fail(AIDW_EINVAL, "area must be finite and > 0");
@@ -210,7 +227,8 @@ constexpr int64_t kGridPass2Segment = 131072;
 
 aidw::SplitPlan grid_pass2_plan(const aidw_ctx* h, const aidw_tuning& t, int64_t m, int64_t n) {
     aidw::SplitPlan sp = split_plan_for(h, t, m, n);
-    if (t.split_segments != 0 || sp.segments > 1) return sp;
+    if (h->deterministic) sp = aidw::SplitPlan{1, (int)m, sp.tiles};  // by m alone
+    else if (t.split_segments != 0 || sp.segments > 1) return sp;
     const int64_t want = std::min<int64_t>(8, m / kGridPass2Segment);
     if (want < 2) return sp;
     int64_t seg = (m + want - 1) / want;
@@ -242,6 +260,15 @@ aidw::ProblemF32 problem_f32(const aidw_problem* p) {
     const float* qxy = static_cast<const float*>(p->query_xy);
     return aidw::ProblemF32{xy, xy + m, static_cast<const float*>(p->data_z), qxy, qxy + n,
                             static_cast<float*>(p->out), p->r_obs, p->alpha, p->knn_idx, m, n,
+                            alpha_params(p)};
+}
+
+aidw::ProblemF64 problem_f64(const aidw_problem* p) {
+    const int m = (int)p->m, n = (int)p->n;
+    const double* xy = static_cast<const double*>(p->data_xy);
+    const double* qxy = static_cast<const double*>(p->query_xy);
+    return aidw::ProblemF64{xy, xy + m, static_cast<const double*>(p->data_z), qxy, qxy + n,
+                            static_cast<double*>(p->out), p->r_obs, p->alpha, p->knn_idx, m, n,
                             alpha_params(p)};
 }
 
@@ -302,7 +329,6 @@ aidw_status run_problem(aidw_t h, const aidw_problem* p) {
     aidw_status st = validate(p);
     if (st != AIDW_OK) return st;
     if (p->n == 0) return AIDW_OK;
-    const aidw::AlphaParams ap = alpha_params(p);
     hipError_t e;
     const int m = (int)p->m, n = (int)p->n;
     if (p->flags & AIDW_FLAG_GRID_KNN) {
@@ -316,8 +342,10 @@ aidw_status run_problem(aidw_t h, const aidw_problem* p) {
         aidw::ProblemF32 q = problem_f32(p);
         aidw_tuning t = h->tuning;
         aidw_tuning tuned;
-        if (!t.q_per_lane && !t.max_waves_per_simd && !t.split_segments &&
-            tuned_shape(h, m, n, p->k, &tuned))
+        if (h->deterministic)
+            t = aidw_tuning{1, 0, 1};  // the unsplit one-query-per-lane kernel
+        else if (!t.q_per_lane && !t.max_waves_per_simd && !t.split_segments &&
+                 tuned_shape(h, m, n, p->k, &tuned))
             t = tuned;
         aidw::LaunchF32 cfg{t.q_per_lane ? t.q_per_lane : default_q_per_lane(h, n),
                             t.max_waves_per_simd};
@@ -337,11 +365,7 @@ aidw_status run_problem(aidw_t h, const aidw_problem* p) {
         e = aidw::launch_abs_max(q.dz, m, zmax, h->stream);
         if (e == hipSuccess) e = aidw::launch_aidw_f32(q, cfg, &sp, &ws, h->stream);
     } else {
-        const double* xy = static_cast<const double*>(p->data_xy);
-        const double* qxy = static_cast<const double*>(p->query_xy);
-        aidw::ProblemF64 q{xy, xy + m, static_cast<const double*>(p->data_z), qxy, qxy + n,
-                           static_cast<double*>(p->out), p->r_obs, p->alpha, p->knn_idx, m, n, ap};
-        e = aidw::launch_aidw_f64(q, h->stream);
+        e = aidw::launch_aidw_f64(problem_f64(p), h->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     if (!(p->flags & AIDW_FLAG_ASYNC)) {
@@ -373,6 +397,7 @@ aidw_status aidw_create(aidw_t* out, const aidw_options* opt) {
     if (!h) return fail(AIDW_ENOMEM, "host allocation failed");
     h->device = o.device;
     h->default_precision = o.default_precision;
+    h->deterministic = o.deterministic != 0;
     h->hbm_budget = o.hbm_budget_bytes;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, o.device) == hipSuccess)
@@ -391,12 +416,16 @@ aidw_status aidw_create(aidw_t* out, const aidw_options* opt) {
 void aidw_destroy(aidw_t h) {
     if (!h) return;
     (void)hipSetDevice(h->device);
+    if (h->server) aidw_server_destroy(h->server);  // finishes its jobs
+    h->server = nullptr;
     (void)hipStreamSynchronize(h->stream);
     device_free(h, h->workspace, h->workspace_bytes);
+    forget_errors(h);
     delete h;
 }
 
 aidw_status aidw_set_stream(aidw_t h, void* stream) {
+    ErrorScope es(h);
     if (!h) return fail(AIDW_EINVAL, "handle is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (s != h->stream) {
@@ -412,6 +441,7 @@ aidw_status aidw_interpolate(aidw_t h, const void* data_xy, const void* data_z, 
                              const void* query_xy, int64_t n, int k,
                              const double alpha_levels[5], double R_min, double R_max,
                              double area, void* out) {
+    ErrorScope es(h);
     if (!h) return fail(AIDW_EINVAL, "handle is NULL");
     if (!alpha_levels) return fail(AIDW_EINVAL, "alpha_levels is NULL");
     aidw_problem p;
@@ -432,11 +462,13 @@ aidw_status aidw_interpolate(aidw_t h, const void* data_xy, const void* data_z, 
 }
 
 aidw_status aidw_interpolate_ex(aidw_t h, const aidw_problem* p) {
+    ErrorScope es(h);
     if (!h) return fail(AIDW_EINVAL, "handle is NULL");
     return run_problem(h, p);
 }
 
 aidw_status aidw_idw(aidw_t h, const aidw_problem* p, double power) {
+    ErrorScope es(h);
     if (!h) return fail(AIDW_EINVAL, "handle is NULL");
     if (!p) return fail(AIDW_EINVAL, "problem is NULL");
     if (!std::isfinite(power) || power < 0.0)
@@ -452,6 +484,7 @@ aidw_status aidw_idw(aidw_t h, const aidw_problem* p, double power) {
 
 aidw_status aidw_interpolate_variant(aidw_t h, const aidw_problem* p, aidw_access access,
                                      aidw_layout layout) {
+    ErrorScope es(h);
     if (!h) return fail(AIDW_EINVAL, "handle is NULL");
     aidw_status st = validate(p);
     if (st != AIDW_OK) return st;
@@ -478,6 +511,7 @@ aidw_status aidw_interpolate_variant(aidw_t h, const aidw_problem* p, aidw_acces
 }
 
 aidw_status aidw_set_tuning(aidw_t h, const aidw_tuning* t) {
+    ErrorScope es(h);
     if (!h) return fail(AIDW_EINVAL, "handle is NULL");
     if (!t) {
         h->tuning = aidw_tuning{0, 0, 0};
@@ -493,12 +527,17 @@ aidw_status aidw_set_tuning(aidw_t h, const aidw_tuning* t) {
 }
 
 aidw_status aidw_synchronize(aidw_t h) {
+    ErrorScope es(h);
     if (!h) return fail(AIDW_EINVAL, "handle is NULL");
     hipError_t e = hipStreamSynchronize(h->stream);
     return e == hipSuccess ? AIDW_OK : hip_fail(e, "hipStreamSynchronize");
 }
 
-const char* aidw_last_error(void) { return g_last_error.c_str(); }
+const char* aidw_last_error(aidw_t h) {
+    if (!h) return g_last_error.c_str();
+    auto it = g_handle_error.find(h);
+    return it == g_handle_error.end() ? "" : it->second.c_str();
+}
 
 const char* aidw_status_string(aidw_status s) {
     switch (s) {
@@ -530,7 +569,7 @@ aidw_status batch_build(aidw_t h, const aidw_problem* problems, int count, aidw_
         const aidw_problem* p = &problems[i];
         aidw_status st = validate(p);
         if (st != AIDW_OK)
-            return fail(st, "problem %d: %s", i, aidw_last_error());
+            return fail(st, "problem %d: %s", i, std::string(aidw_last_error(nullptr)).c_str());
         if (p->precision != AIDW_FP32_SCALED)
             return fail(AIDW_EINVAL, "problem %d: batched problems must be AIDW_FP32_SCALED", i);
         if (p->knn_idx)
@@ -615,6 +654,7 @@ extern "C" {
 
 aidw_status aidw_batch_create(aidw_t h, const aidw_problem* problems, int count,
                               aidw_batch_t* out) {
+    ErrorScope es(h);
     if (!h || !out) return fail(AIDW_EINVAL, "handle or out is NULL");
     *out = nullptr;
     aidw_batch* b = new (std::nothrow) aidw_batch;
@@ -631,6 +671,7 @@ aidw_status aidw_batch_create(aidw_t h, const aidw_problem* problems, int count,
 }
 
 aidw_status aidw_batch_launch(aidw_batch_t b, unsigned flags) {
+    ErrorScope es(b ? b->h : nullptr);
     if (!b) return fail(AIDW_EINVAL, "batch is NULL");
     if (b->launch.n_items == 0) return AIDW_OK;
     hipError_t e = hipGraphLaunch(b->exec, b->h->stream);
@@ -643,6 +684,7 @@ aidw_status aidw_batch_launch(aidw_batch_t b, unsigned flags) {
 }
 
 void aidw_batch_destroy(aidw_batch_t b) {
+    ErrorScope es(b ? b->h : nullptr);
     if (!b) return;
     if (b->h) (void)hipStreamSynchronize(b->h->stream);
     batch_release(b);
@@ -651,6 +693,7 @@ void aidw_batch_destroy(aidw_batch_t b) {
 
 aidw_status aidw_interpolate_batch(aidw_t h, const aidw_problem* problems, int count,
                                    unsigned flags) {
+    ErrorScope es(h);
     if (!h) return fail(AIDW_EINVAL, "handle is NULL");
     aidw_batch b;
     aidw_status st = batch_build(h, problems, count, &b);

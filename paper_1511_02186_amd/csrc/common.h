@@ -140,9 +140,13 @@ struct ServeLaunch {
     int n_tasks;
     int n_items;
     int K;
+    bool track;                 // every item is a fused item of a job that wants knn_idx
 };
 
 hipError_t launch_aidw_f32_serve(const ServeLaunch& s, hipStream_t stream);
+// FP64 jobs of a tick: one wave per (job, 64-query tile) item, phase ignored.
+hipError_t launch_aidw_f64_serve(const ProblemF64* jobs, const ServeItem* items, int n_items,
+                                 int K, bool track, hipStream_t stream);
 
 // ---- k nearest through a uniform grid (pass 1 without the full scan) -------
 struct GridGeom {

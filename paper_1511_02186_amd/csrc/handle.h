@@ -28,9 +28,12 @@ struct TuneEntry {
     double ms;
 };
 
+struct aidw_server;
+
 struct aidw_ctx {
     int device = 0;
     aidw_precision default_precision = AIDW_FP32_SCALED;
+    bool deterministic = false;   // fixed launch shape for FP32-scaled problems
     size_t hbm_budget = 0;        // 0: unlimited
     size_t hbm_in_use = 0;        // library-owned device bytes
     hipStream_t stream = nullptr;
@@ -44,16 +47,38 @@ struct aidw_ctx {
     std::unordered_map<uint64_t, aidw_dataset_rec> datasets;
     uint64_t next_dataset = 1;
     std::vector<TuneEntry> tune_table;  // consulted when `tuning` is all automatic
+    // The handle's own serving loop (aidw_submit / aidw_poll), created on first use.
+    std::mutex server_mu;
+    aidw_server* server = nullptr;
 };
 
 namespace aidw {
 namespace detail {
 
+// Record an error message for the calling thread (and for the handle of the
+// innermost ErrorScope) and return s.
 aidw_status fail(aidw_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+// Every public entry point that works on a handle opens one: errors raised
+// while it is alive are also kept as the handle's message for this thread
+// (aidw_last_error(h)).
+class ErrorScope {
+   public:
+    explicit ErrorScope(const aidw_ctx* h);
+    ~ErrorScope();
+    ErrorScope(const ErrorScope&) = delete;
+    ErrorScope& operator=(const ErrorScope&) = delete;
+
+   private:
+    const aidw_ctx* prev_;
+};
+// Forget the calling thread's message for h (the handle is being destroyed).
+void forget_errors(const aidw_ctx* h);
 aidw_status hip_fail(hipError_t e, const char* what);
 aidw_status validate(const aidw_problem* p);
 AlphaParams alpha_params(const aidw_problem* p);
 ProblemF32 problem_f32(const aidw_problem* p);
+ProblemF64 problem_f64(const aidw_problem* p);
 aidw_status device_alloc(aidw_t h, size_t bytes, void** out);
 void device_free(aidw_t h, void* p, size_t bytes);
 // Bytes of a split workspace; with ws/base given, also lays it out at base.

@@ -599,6 +599,12 @@ __device__ __forceinline__ void merge_tile(const ProblemF32& p, const SplitPlan&
 }
 
 // ---- split-m ------------------------------------------------------------------
+// End of the segment that starts at j0 (< m), formed in 64 bits: j0 + seg_len
+// can pass 2^31 for the largest m.
+__device__ __forceinline__ int seg_end(int m, int j0, int seg_len) {
+    return (int)min((int64_t)m, (int64_t)j0 + seg_len);
+}
+
 // Waves are numbered segment-major so that the waves of one workgroup share a
 // data segment.
 template <int K>
@@ -609,7 +615,7 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_knn_part(ProblemF32 p, Sp
     const int tile = wave - seg * sp.tiles;
     if (seg >= sp.segments) return;
     const int j0 = seg * sp.seg_len;
-    const int j1 = min(p.m, j0 + sp.seg_len);
+    const int j1 = seg_end(p.m, j0, sp.seg_len);
     int qi[1];
     float qx[1], qy[1];
     load_queries<1>(p, tile * kWaveSize, qi, qx, qy);
@@ -639,7 +645,7 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_wsum_part(ProblemF32 p, S
     const int tile = wave - seg * sp.tiles;
     if (seg >= sp.segments) return;
     const int j0 = seg * sp.seg_len;
-    const int j1 = min(p.m, j0 + sp.seg_len);
+    const int j1 = seg_end(p.m, j0, sp.seg_len);
     int qi[1];
     float qx[1], qy[1];
     load_queries<1>(p, tile * kWaveSize, qi, qx, qy);
@@ -720,7 +726,7 @@ __device__ __forceinline__ void serve_item(const ServeJob& J, const ServeItem& i
         return;
     }
     const int j0 = it.seg * J.sp.seg_len;
-    const int j1 = min(p.m, j0 + J.sp.seg_len);
+    const int j1 = seg_end(p.m, j0, J.sp.seg_len);
     int qi[1];
     float qx[1], qy[1];
     load_queries<1>(p, it.tile * kWaveSize, qi, qx, qy);
@@ -753,14 +759,17 @@ __device__ __forceinline__ void serve_item(const ServeJob& J, const ServeItem& i
     }
 }
 
-template <int K>
+template <int K, bool TRACK>
 __global__ __launch_bounds__(kGroupSize) void aidw_f32_serve(const ServeJob* __restrict__ jobs,
                                                              const ServeItem* __restrict__ items,
                                                              int n_items) {
     const int it = wave_id();
     if (it >= n_items) return;
     const ServeItem w = items[it];
-    serve_item<K>(jobs[w.job], w);
+    if constexpr (TRACK)
+        fused_tile<K, 1, true>(jobs[w.job].p, w.tile * kWaveSize);  // jobs with knn_idx: unsplit
+    else
+        serve_item<K>(jobs[w.job], w);
 }
 
 // ---- host-side launchers ----------------------------------------------------------
@@ -837,8 +846,12 @@ hipError_t launch_serve_k(const ServeLaunch& sl, hipStream_t stream) {
     if (sl.n_tasks > 0)
         hipLaunchKernelGGL(aidw_abs_max_tasks, dim3((unsigned)sl.n_tasks), dim3(256), 0, stream,
                            sl.tasks);
-    hipLaunchKernelGGL((aidw_f32_serve<K>), dim3(groups_for(sl.n_items)), dim3(kGroupSize), 0,
-                       stream, sl.jobs, sl.items, sl.n_items);
+    if (sl.track)
+        hipLaunchKernelGGL((aidw_f32_serve<K, true>), dim3(groups_for(sl.n_items)),
+                           dim3(kGroupSize), 0, stream, sl.jobs, sl.items, sl.n_items);
+    else
+        hipLaunchKernelGGL((aidw_f32_serve<K, false>), dim3(groups_for(sl.n_items)),
+                           dim3(kGroupSize), 0, stream, sl.jobs, sl.items, sl.n_items);
     return hipGetLastError();
 }
 

@@ -39,15 +39,21 @@ struct Neumaier {
     __device__ __forceinline__ double value() const { return s + c; }
 };
 
+// Data are read through the constant address space: at wave-uniform
+// addresses such loads are scalar, also when the problem itself was loaded
+// from memory (a serving job descriptor).
+typedef const __attribute__((address_space(4))) double* cptr64;
+
+// One query (index qi; lanes with qi >= n compute a clamped copy and store
+// nothing): both passes over all m points.
 template <int K, bool TRACK>
-__global__ __launch_bounds__(kGroupSize) void aidw_f64_plain(ProblemF64 p) {
-    const int qi = blockIdx.x * kGroupSize + threadIdx.x;
+__device__ __forceinline__ void f64_query(const ProblemF64& p, int qi) {
     const int c = qi < p.n ? qi : p.n - 1;
     const double qx = p.qx[c], qy = p.qy[c];
     const int m = p.m;
-    const double* __restrict__ X = p.dx;
-    const double* __restrict__ Y = p.dy;
-    const double* __restrict__ Z = p.dz;
+    const cptr64 X = (cptr64)p.dx;
+    const cptr64 Y = (cptr64)p.dy;
+    const cptr64 Z = (cptr64)p.dz;
 
     const int pad = K - p.ap.k;
     double top[K];
@@ -122,6 +128,22 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f64_plain(ProblemF64 p) {
     }
 }
 
+template <int K, bool TRACK>
+__global__ __launch_bounds__(kGroupSize) void aidw_f64_plain(ProblemF64 p) {
+    f64_query<K, TRACK>(p, (int)(blockIdx.x * kGroupSize + threadIdx.x));
+}
+
+// Serving: one wave per (job, 64-query tile) item.
+template <int K, bool TRACK>
+__global__ __launch_bounds__(kGroupSize) void aidw_f64_serve(const ProblemF64* __restrict__ jobs,
+                                                             const ServeItem* __restrict__ items,
+                                                             int n_items) {
+    const int it = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6));
+    if (it >= n_items) return;
+    const ServeItem w = items[it];
+    f64_query<K, TRACK>(jobs[w.job], w.tile * kWaveSize + (int)(threadIdx.x & (kWaveSize - 1)));
+}
+
 template <int K>
 hipError_t launch_k(const ProblemF64& p, hipStream_t stream) {
     const int64_t groups = (p.n + kGroupSize - 1) / kGroupSize;
@@ -134,7 +156,36 @@ hipError_t launch_k(const ProblemF64& p, hipStream_t stream) {
     return hipGetLastError();
 }
 
+template <int K>
+hipError_t launch_serve_k(const ProblemF64* jobs, const ServeItem* items, int n_items, bool track,
+                          hipStream_t stream) {
+    const unsigned groups = (unsigned)((n_items + kWavesPerGroup - 1) / kWavesPerGroup);
+    if (track)
+        hipLaunchKernelGGL((aidw_f64_serve<K, true>), dim3(groups), dim3(kGroupSize), 0, stream,
+                           jobs, items, n_items);
+    else
+        hipLaunchKernelGGL((aidw_f64_serve<K, false>), dim3(groups), dim3(kGroupSize), 0, stream,
+                           jobs, items, n_items);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_aidw_f64_serve(const ProblemF64* jobs, const ServeItem* items, int n_items,
+                                 int K, bool track, hipStream_t stream) {
+    if (n_items <= 0) return hipSuccess;
+    switch (K) {
+        case 4: return launch_serve_k<4>(jobs, items, n_items, track, stream);
+        case 8: return launch_serve_k<8>(jobs, items, n_items, track, stream);
+        case 10: return launch_serve_k<10>(jobs, items, n_items, track, stream);
+        case 12: return launch_serve_k<12>(jobs, items, n_items, track, stream);
+        case 16: return launch_serve_k<16>(jobs, items, n_items, track, stream);
+        case 20: return launch_serve_k<20>(jobs, items, n_items, track, stream);
+        case 24: return launch_serve_k<24>(jobs, items, n_items, track, stream);
+        case 32: return launch_serve_k<32>(jobs, items, n_items, track, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_aidw_f64(const ProblemF64& p, hipStream_t stream) {
     if (p.n <= 0) return hipSuccess;

@@ -86,6 +86,7 @@ hipError_t time_probe(hipStream_t s, int blocks, float* out, const float* src, i
 extern "C" {
 
 aidw_status aidw_probe_issue_costs(aidw_t h, aidw_issue_costs* out) {
+    ErrorScope es(h);
     if (!h || !out) return fail(AIDW_EINVAL, "handle or out is NULL");
     int clock_khz = 0;
     if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeClockRate, h->device) != hipSuccess ||

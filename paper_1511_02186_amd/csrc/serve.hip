@@ -2,9 +2,10 @@
 // polling, and the HIP executor that turns each scheduling tick into one
 // launch of the serving kernel (declared in include/aidw.h).
 //
-// Threads: client threads call aidw_submit / aidw_poll / aidw_wait; one
-// worker thread per server runs the scheduler.  Every scheduler and executor
-// call happens under the server's mutex.
+// Threads: client threads call aidw_server_submit / _poll / _wait (or the
+// handle-level aidw_submit / aidw_poll / aidw_wait); one worker thread per
+// server runs the scheduler.  Every scheduler and executor call happens
+// under the server's mutex.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -28,14 +29,22 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// Device time of a plain FP64 distance evaluation relative to an
+// FP32-scaled one (the FP64 kernel runs about 20x slower per pair); the
+// scheduler weighs FP64 jobs by it against the tick quota.
+constexpr double kF64CostScale = 20.0;
+
 struct JobRec {
-    aidw::ProblemF32 p{};
+    aidw_precision precision = AIDW_FP32_SCALED;
+    aidw::ProblemF32 p{};       // FP32-scaled jobs
+    aidw::ProblemF64 p64{};     // FP64 jobs
     aidw::SplitPlan sp{};
     int K = 4;
+    bool track = false;         // knn_idx wanted: fused items only, index-tracking kernel
     size_t ws_bytes = 0;        // split workspace, then the two arrival-counter arrays
     size_t counters_off = 0;    // offset of the counters inside the job's workspace
     char* ws = nullptr;         // device address of the job's workspace
-    bool counters_zeroed = false;
+    uint64_t zero_seq = 0;      // admin-stream sequence number that cleared its counters
     uint64_t dataset = 0;
 };
 
@@ -43,12 +52,15 @@ struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool launched = false;
-    bool failed = false;
-    void* host = nullptr;  // pinned staging of the tick's jobs and items
+    uint64_t admin_seen = 0;  // admin-stream work this stream has been ordered after
+    void* host = nullptr;     // pinned staging of the tick's jobs and items
     size_t host_cap = 0;
     void* dev = nullptr;
     size_t dev_cap = 0;
 };
+
+// Item kinds of a tick, one kernel launch each (on the tick's stream).
+enum Kind { kF32 = 0, kF32Track = 1, kF64 = 2, kF64Track = 3, kKinds = 4 };
 
 class HipExecutor : public sv::Executor {
    public:
@@ -57,6 +69,12 @@ class HipExecutor : public sv::Executor {
     size_t arena_bytes = 0;
     std::unordered_map<uint64_t, JobRec> jobs;
     std::vector<Slot> slots;
+    // Split jobs' arrival counters are cleared on this stream when the job
+    // is admitted; every slot stream waits for `admin_done` before it runs a
+    // tick that carries a job it has not yet been ordered after.
+    hipStream_t admin = nullptr;
+    hipEvent_t admin_done = nullptr;
+    uint64_t admin_seq = 0;
     aidw_status error = AIDW_OK;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
@@ -66,7 +84,16 @@ class HipExecutor : public sv::Executor {
 
     int admit(uint64_t t, size_t off) override {
         JobRec& r = jobs[t];
-        if (r.sp.segments > 1) r.ws = arena + off;
+        if (r.sp.segments <= 1) return 0;
+        r.ws = arena + off;
+        hipError_t e = hipMemsetAsync(r.ws + r.counters_off, 0,
+                                      2 * sizeof(int) * (size_t)r.sp.tiles, admin);
+        if (e == hipSuccess) e = hipEventRecord(admin_done, admin);
+        if (e != hipSuccess) {
+            error = hip_fail(e, "arrival counter clearing");
+            return AIDW_EDEVICE;
+        }
+        r.zero_seq = ++admin_seq;
         return 0;
     }
 
@@ -74,9 +101,16 @@ class HipExecutor : public sv::Executor {
         Slot& s = slots[(size_t)slot];
         std::unordered_map<uint64_t, int> index;
         std::vector<aidw::ServeJob> sj;
-        int K = 4;
+        std::vector<aidw::ProblemF64> sj64;
+        uint64_t need_seq = 0;
         for (uint64_t t : plan.jobs) {
             JobRec& r = jobs[t];
+            need_seq = std::max(need_seq, r.zero_seq);
+            if (r.precision == AIDW_FP64) {
+                index[t] = (int)sj64.size();
+                sj64.push_back(r.p64);
+                continue;
+            }
             index[t] = (int)sj.size();
             aidw::ServeJob j{};
             j.p = r.p;
@@ -87,19 +121,32 @@ class HipExecutor : public sv::Executor {
                 j.sum_arrivals = j.knn_arrivals + r.sp.tiles;
             }
             sj.push_back(j);
-            K = std::max(K, r.K);
         }
-        std::vector<aidw::ServeItem> items(plan.items.size());
-        for (size_t i = 0; i < plan.items.size(); ++i) {
-            const sv::Item& it = plan.items[i];
-            items[i] = aidw::ServeItem{index[it.ticket], it.phase, it.tile, it.seg};
+        // items grouped by kernel, each group in plan order
+        std::vector<aidw::ServeItem> items[kKinds];
+        int K[kKinds] = {4, 4, 4, 4};
+        for (const sv::Item& it : plan.items) {
+            const JobRec& r = jobs[it.ticket];
+            const int kind = (r.precision == AIDW_FP64 ? kF64 : kF32) + (r.track ? 1 : 0);
+            items[kind].push_back(aidw::ServeItem{index[it.ticket], it.phase, it.tile, it.seg});
+            K[kind] = std::max(K[kind], r.K);
         }
-        // staging: jobs | items | max-|z| tasks | max-|z| slots (one per job,
-        // recomputed by every tick that carries the job, on the tick's own stream)
-        const size_t b_jobs = align_up(sizeof(aidw::ServeJob) * sj.size());
-        const size_t b_items = align_up(sizeof(aidw::ServeItem) * items.size());
-        const size_t b_tasks = align_up(sizeof(aidw::AbsMaxTask) * sj.size());
-        const size_t o_tasks = b_jobs + b_items, o_z = o_tasks + b_tasks;
+        // staging: f32 jobs | f64 jobs | items of each kind | max-|z| tasks |
+        // max-|z| slots (one per f32 job, recomputed by every tick that
+        // carries the job, on the tick's own stream)
+        size_t off = 0;
+        const size_t o_jobs = off;
+        off += align_up(sizeof(aidw::ServeJob) * sj.size());
+        const size_t o_jobs64 = off;
+        off += align_up(sizeof(aidw::ProblemF64) * sj64.size());
+        size_t o_items[kKinds];
+        for (int k = 0; k < kKinds; ++k) {
+            o_items[k] = off;
+            off += align_up(sizeof(aidw::ServeItem) * items[k].size());
+        }
+        const size_t o_tasks = off;
+        off += align_up(sizeof(aidw::AbsMaxTask) * sj.size());
+        const size_t o_z = off;
         const size_t bytes = o_z + align_up(sizeof(float) * sj.size());
         if (grow(s, bytes) != AIDW_OK) return AIDW_ENOMEM;
         char* host = static_cast<char*>(s.host);
@@ -110,33 +157,46 @@ class HipExecutor : public sv::Executor {
             sj[i].p.zmax = zslots + i;
             tasks[i] = aidw::AbsMaxTask{sj[i].p.dz, zslots + i, sj[i].p.m};
         }
-        memcpy(host, sj.data(), sizeof(aidw::ServeJob) * sj.size());
-        memcpy(host + b_jobs, items.data(), sizeof(aidw::ServeItem) * items.size());
-        memcpy(host + o_tasks, tasks.data(), sizeof(aidw::AbsMaxTask) * tasks.size());
-        hipError_t e = hipMemcpyAsync(dev, host, b_jobs + b_items, hipMemcpyHostToDevice, s.stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(dev + o_tasks, host + o_tasks, sizeof(aidw::AbsMaxTask) * tasks.size(),
-                               hipMemcpyHostToDevice, s.stream);
-        // arrival counters start at zero before a split job's first item
-        for (uint64_t t : plan.jobs) {
-            JobRec& r = jobs[t];
-            if (e != hipSuccess || r.sp.segments <= 1 || r.counters_zeroed) continue;
-            e = hipMemsetAsync(r.ws + r.counters_off, 0, 2 * sizeof(int) * (size_t)r.sp.tiles,
-                               s.stream);
-            r.counters_zeroed = true;
+        if (!sj.empty()) memcpy(host + o_jobs, sj.data(), sizeof(aidw::ServeJob) * sj.size());
+        if (!sj64.empty())
+            memcpy(host + o_jobs64, sj64.data(), sizeof(aidw::ProblemF64) * sj64.size());
+        for (int k = 0; k < kKinds; ++k)
+            if (!items[k].empty())
+                memcpy(host + o_items[k], items[k].data(), sizeof(aidw::ServeItem) * items[k].size());
+        if (!tasks.empty())
+            memcpy(host + o_tasks, tasks.data(), sizeof(aidw::AbsMaxTask) * tasks.size());
+        hipError_t e = hipMemcpyAsync(dev, host, o_z, hipMemcpyHostToDevice, s.stream);
+        // the counters of every split job in this tick were cleared on the
+        // admin stream: order this stream after that
+        if (e == hipSuccess && need_seq > s.admin_seen) {
+            e = hipStreamWaitEvent(s.stream, admin_done, 0);
+            s.admin_seen = admin_seq;
         }
         if (e != hipSuccess) {
             error = hip_fail(e, "tick upload");
             return AIDW_EDEVICE;
         }
-        aidw::ServeLaunch sl{};
-        sl.jobs = reinterpret_cast<const aidw::ServeJob*>(dev);
-        sl.items = reinterpret_cast<const aidw::ServeItem*>(dev + b_jobs);
-        sl.tasks = reinterpret_cast<const aidw::AbsMaxTask*>(dev + o_tasks);
-        sl.n_tasks = (int)tasks.size();
-        sl.n_items = (int)items.size();
-        sl.K = aidw::k_bucket(K);
-        e = aidw::launch_aidw_f32_serve(sl, s.stream);
+        int tasks_left = (int)tasks.size();  // max |z| runs before the first f32 launch
+        for (int k = kF32; k <= kF32Track && e == hipSuccess; ++k) {
+            if (items[k].empty()) continue;
+            aidw::ServeLaunch sl{};
+            sl.jobs = reinterpret_cast<const aidw::ServeJob*>(dev + o_jobs);
+            sl.items = reinterpret_cast<const aidw::ServeItem*>(dev + o_items[k]);
+            sl.tasks = reinterpret_cast<const aidw::AbsMaxTask*>(dev + o_tasks);
+            sl.n_tasks = tasks_left;
+            sl.n_items = (int)items[k].size();
+            sl.K = aidw::k_bucket(K[k]);
+            sl.track = k == kF32Track;
+            e = aidw::launch_aidw_f32_serve(sl, s.stream);
+            tasks_left = 0;
+        }
+        for (int k = kF64; k <= kF64Track && e == hipSuccess; ++k) {
+            if (items[k].empty()) continue;
+            e = aidw::launch_aidw_f64_serve(
+                reinterpret_cast<const aidw::ProblemF64*>(dev + o_jobs64),
+                reinterpret_cast<const aidw::ServeItem*>(dev + o_items[k]), (int)items[k].size(),
+                aidw::k_bucket(K[k]), k == kF64Track, s.stream);
+        }
         if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
         if (e != hipSuccess) {
             error = hip_fail(e, "tick launch");
@@ -226,13 +286,15 @@ namespace {
 aidw_status prepare_job(aidw_server* s, const aidw_job* job, JobRec* out, sv::JobSpec* spec_out) {
     aidw_problem p;
     memset(&p, 0, sizeof p);
-    p.precision = AIDW_FP32_SCALED;
+    p.precision = job->precision;
     p.data_xy = job->data_xy;
     p.data_z = job->data_z;
     p.m = job->m;
     p.area = job->area;
     aidw_t h = s->h;
     if (job->dataset) {
+        if (job->precision != AIDW_FP32_SCALED)
+            return fail(AIDW_EINVAL, "registered data sets hold FP32 data: FP32-scaled jobs only");
         std::lock_guard<std::mutex> lk(h->mu);
         auto it = h->datasets.find(job->dataset);
         if (it == h->datasets.end())
@@ -251,29 +313,49 @@ aidw_status prepare_job(aidw_server* s, const aidw_job* job, JobRec* out, sv::Jo
     p.out = job->out;
     p.r_obs = job->r_obs;
     p.alpha = job->alpha;
+    p.knn_idx = job->knn_idx;
     aidw_status st = validate(&p);
     if (st != AIDW_OK) return st;
 
     JobRec r;
-    r.p = problem_f32(&p);
+    r.precision = p.precision;
     r.K = aidw::k_bucket(p.k);
+    r.track = p.knn_idx != nullptr;
     r.sp = aidw::SplitPlan{1, (int)p.m, (int)((p.n + 63) / 64)};
     sv::JobSpec spec;
     spec.m = p.m;
     spec.n = p.n;
-    const int64_t seg = (s->opt.segment_points + 31) / 32 * 32;
-    if (p.m > seg && p.n > 0) {
-        r.sp.seg_len = (int)seg;
-        r.sp.segments = (int)((p.m + seg - 1) / seg);
-        r.counters_off = align_up(split_workspace_bytes(r.sp, p.k, p.n, nullptr, nullptr));
-        r.ws_bytes = r.counters_off + 2 * sizeof(int) * (size_t)r.sp.tiles;
-        spec.segments = r.sp.segments;
-        spec.seg_len = seg;
-        spec.ws_bytes = r.ws_bytes;
+    if (p.precision == AIDW_FP64) {
+        // the plain FP64 kernel, 64-query tiles over all m points
+        r.p64 = problem_f64(&p);
+        spec.cost_scale = kF64CostScale;
+    } else {
+        r.p = problem_f32(&p);
+        const int64_t seg = (s->opt.segment_points + 31) / 32 * 32;
+        if (p.m > seg && p.n > 0 && !r.track) {
+            r.sp.seg_len = (int)seg;
+            r.sp.segments = (int)((p.m + seg - 1) / seg);
+            r.counters_off = align_up(split_workspace_bytes(r.sp, p.k, p.n, nullptr, nullptr));
+            r.ws_bytes = r.counters_off + 2 * sizeof(int) * (size_t)r.sp.tiles;
+            spec.segments = r.sp.segments;
+            spec.seg_len = seg;
+            spec.ws_bytes = r.ws_bytes;
+        }
     }
     r.dataset = job->dataset;
     *out = r;
     *spec_out = spec;
+    return AIDW_OK;
+}
+
+// The handle's own serving loop, created with default options on first use.
+aidw_status handle_server(aidw_t h, bool create, aidw_server** out) {
+    std::lock_guard<std::mutex> lk(h->server_mu);
+    if (!h->server && create) {
+        aidw_status st = aidw_server_create(h, nullptr, &h->server);
+        if (st != AIDW_OK) return st;
+    }
+    *out = h->server;
     return AIDW_OK;
 }
 
@@ -283,9 +365,11 @@ extern "C" {
 
 aidw_status aidw_dataset_register(aidw_t h, const void* data_xy, const void* data_z, int64_t m,
                                   double area, uint64_t* id) {
+    ErrorScope es(h);
     if (!h || !id) return fail(AIDW_EINVAL, "handle or id is NULL");
     *id = 0;
-    if (m < 1 || m > INT32_MAX) return fail(AIDW_EINVAL, "m = %lld out of [1, 2^31-1]", (long long)m);
+    if (m < 1 || m > AIDW_MAX_POINTS)
+        return fail(AIDW_EINVAL, "m = %lld out of [1, %lld]", (long long)m, (long long)AIDW_MAX_POINTS);
     if (!std::isfinite(area) || area <= 0.0) return fail(AIDW_EINVAL, "area must be finite and > 0");
     if (!data_xy || !data_z) return fail(AIDW_EINVAL, "NULL data pointer");
     if ((uintptr_t)data_xy % 4 || (uintptr_t)data_z % 4)
@@ -319,6 +403,7 @@ aidw_status aidw_dataset_register(aidw_t h, const void* data_xy, const void* dat
 }
 
 aidw_status aidw_dataset_release(aidw_t h, uint64_t id) {
+    ErrorScope es(h);
     if (!h) return fail(AIDW_EINVAL, "handle is NULL");
     aidw_dataset_rec r;
     {
@@ -336,6 +421,7 @@ aidw_status aidw_dataset_release(aidw_t h, uint64_t id) {
 }
 
 aidw_status aidw_server_create(aidw_t h, const aidw_server_options* opt, aidw_server_t* out) {
+    ErrorScope es(h);
     if (!h || !out) return fail(AIDW_EINVAL, "handle or out is NULL");
     *out = nullptr;
     aidw_server_options o{};
@@ -360,6 +446,15 @@ aidw_status aidw_server_create(aidw_t h, const aidw_server_options* opt, aidw_se
     s->ex.arena = static_cast<char*>(arena);
     s->ex.arena_bytes = o.arena_bytes;
     s->ex.slots.resize((size_t)o.streams);
+    {
+        hipError_t e = hipStreamCreateWithFlags(&s->ex.admin, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ex.admin_done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "stream or event creation");
+            aidw_server_destroy(s);
+            return st;
+        }
+    }
     for (Slot& sl : s->ex.slots) {
         hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
@@ -401,18 +496,23 @@ void aidw_server_destroy(aidw_server_t s) {
         if (sl.host) (void)hipHostFree(sl.host);
         device_free(s->h, sl.dev, sl.dev_cap);
     }
+    if (s->ex.admin) (void)hipStreamSynchronize(s->ex.admin);
+    if (s->ex.admin_done) (void)hipEventDestroy(s->ex.admin_done);
+    if (s->ex.admin) (void)hipStreamDestroy(s->ex.admin);
     device_free(s->h, s->ex.arena, s->ex.arena_bytes);
     delete s->sched;
     delete s;
 }
 
-aidw_status aidw_submit(aidw_server_t s, const aidw_job* job, uint64_t* ticket) {
+aidw_status aidw_server_submit(aidw_server_t s, const aidw_job* job, uint64_t* ticket) {
+    ErrorScope es(s ? s->h : nullptr);
     if (!s || !job || !ticket) return fail(AIDW_EINVAL, "server, job or ticket is NULL");
-    return aidw_submit_batch(s, job, 1, ticket);
+    return aidw_server_submit_batch(s, job, 1, ticket);
 }
 
-aidw_status aidw_submit_batch(aidw_server_t s, const aidw_job* jobs, int count,
-                              uint64_t* tickets) {
+aidw_status aidw_server_submit_batch(aidw_server_t s, const aidw_job* jobs, int count,
+                                     uint64_t* tickets) {
+    ErrorScope es(s ? s->h : nullptr);
     if (!s || count < 0 || (count > 0 && (!jobs || !tickets)))
         return fail(AIDW_EINVAL, "server, jobs or tickets is NULL, or count < 0");
     for (int i = 0; i < count; ++i) tickets[i] = 0;
@@ -421,7 +521,7 @@ aidw_status aidw_submit_batch(aidw_server_t s, const aidw_job* jobs, int count,
     for (int i = 0; i < count; ++i) {
         const aidw_status st = prepare_job(s, &jobs[i], &recs[(size_t)i], &specs[(size_t)i]);
         if (st != AIDW_OK) {
-            const std::string msg = aidw_last_error();
+            const std::string msg = aidw_last_error(nullptr);
             return count == 1 ? fail(st, "%s", msg.c_str())
                               : fail(st, "job %d: %s", i, msg.c_str());
         }
@@ -452,8 +552,9 @@ aidw_status aidw_submit_batch(aidw_server_t s, const aidw_job* jobs, int count,
     return AIDW_OK;
 }
 
-aidw_status aidw_poll(aidw_server_t s, uint64_t ticket, aidw_status* job_status,
-                      double* latency_s) {
+aidw_status aidw_server_poll(aidw_server_t s, uint64_t ticket, aidw_status* job_status,
+                             double* latency_s) {
+    ErrorScope es(s ? s->h : nullptr);
     if (!s) return fail(AIDW_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
     sv::JobState state;
@@ -468,12 +569,12 @@ aidw_status aidw_poll(aidw_server_t s, uint64_t ticket, aidw_status* job_status,
     return AIDW_OK;
 }
 
-aidw_status aidw_wait(aidw_server_t s, uint64_t ticket, double timeout_s, aidw_status* job_status,
-                      double* latency_s) {
+aidw_status aidw_server_wait(aidw_server_t s, uint64_t ticket, double timeout_s,
+                             aidw_status* job_status, double* latency_s) {
     const auto t_end = std::chrono::steady_clock::now() +
                        std::chrono::duration<double>(timeout_s < 0 ? 1e9 : timeout_s);
     for (;;) {
-        aidw_status st = aidw_poll(s, ticket, job_status, latency_s);
+        aidw_status st = aidw_server_poll(s, ticket, job_status, latency_s);
         if (st != AIDW_EAGAIN) return st;
         if (std::chrono::steady_clock::now() >= t_end) return AIDW_EAGAIN;
         std::this_thread::sleep_for(std::chrono::microseconds(50));
@@ -481,6 +582,7 @@ aidw_status aidw_wait(aidw_server_t s, uint64_t ticket, double timeout_s, aidw_s
 }
 
 aidw_status aidw_server_stats(aidw_server_t s, aidw_server_counters* out) {
+    ErrorScope es(s ? s->h : nullptr);
     if (!s || !out) return fail(AIDW_EINVAL, "server or out is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
     const sv::Stats st = s->sched->stats();
@@ -493,6 +595,41 @@ aidw_status aidw_server_stats(aidw_server_t s, aidw_server_counters* out) {
     out->queued = st.queued;
     out->admitted = st.admitted;
     return s->ex.error;
+}
+
+aidw_status aidw_submit(aidw_t h, const aidw_job* job, uint64_t* ticket) {
+    ErrorScope es(h);
+    if (!h) return fail(AIDW_EINVAL, "handle is NULL");
+    aidw_server* s = nullptr;
+    aidw_status st = handle_server(h, true, &s);
+    return st != AIDW_OK ? st : aidw_server_submit(s, job, ticket);
+}
+
+aidw_status aidw_submit_batch(aidw_t h, const aidw_job* jobs, int count, uint64_t* tickets) {
+    ErrorScope es(h);
+    if (!h) return fail(AIDW_EINVAL, "handle is NULL");
+    aidw_server* s = nullptr;
+    aidw_status st = handle_server(h, true, &s);
+    return st != AIDW_OK ? st : aidw_server_submit_batch(s, jobs, count, tickets);
+}
+
+aidw_status aidw_poll(aidw_t h, uint64_t ticket, aidw_status* job_status, double* latency_s) {
+    ErrorScope es(h);
+    if (!h) return fail(AIDW_EINVAL, "handle is NULL");
+    aidw_server* s = nullptr;
+    (void)handle_server(h, false, &s);
+    if (!s) return fail(AIDW_ENOTFOUND, "no ticket %llu", (unsigned long long)ticket);
+    return aidw_server_poll(s, ticket, job_status, latency_s);
+}
+
+aidw_status aidw_wait(aidw_t h, uint64_t ticket, double timeout_s, aidw_status* job_status,
+                      double* latency_s) {
+    ErrorScope es(h);
+    if (!h) return fail(AIDW_EINVAL, "handle is NULL");
+    aidw_server* s = nullptr;
+    (void)handle_server(h, false, &s);
+    if (!s) return fail(AIDW_ENOTFOUND, "no ticket %llu", (unsigned long long)ticket);
+    return aidw_server_wait(s, ticket, timeout_s, job_status, latency_s);
 }
 
 }  // extern "C"

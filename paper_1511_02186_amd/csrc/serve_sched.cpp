@@ -63,9 +63,9 @@ int64_t Scheduler::total_items(const Job& j, int phase) const {
 
 double Scheduler::item_cost(const Job& j, int phase) const {
     // distance evaluations of one item: 64 queries against m (both passes) or
-    // against one segment (one pass)
-    if (phase == kFused) return 2.0 * 64.0 * (double)j.spec.m;
-    return 64.0 * (double)j.spec.seg_len;
+    // against one segment (one pass), weighted by the job's relative cost
+    if (phase == kFused) return 2.0 * 64.0 * (double)j.spec.m * j.spec.cost_scale;
+    return 64.0 * (double)j.spec.seg_len * j.spec.cost_scale;
 }
 
 bool Scheduler::finished(const Job& j) const {
@@ -79,9 +79,10 @@ uint64_t Scheduler::submit(const JobSpec& spec) {
     j.spec = spec;
     if (j.spec.segments < 1) j.spec.segments = 1;
     if (j.spec.seg_len <= 0) j.spec.seg_len = j.spec.m;
+    if (!(j.spec.cost_scale > 0.0)) j.spec.cost_scale = 1.0;
     j.tiles = (spec.n + 63) / 64;
     j.t_submit = ex_->now();
-    j.remaining = 2.0 * (double)spec.m * (double)(j.tiles * 64);
+    j.remaining = 2.0 * (double)spec.m * (double)(j.tiles * 64) * j.spec.cost_scale;
     ++stats_.submitted;
     if (spec.ws_bytes > 0 && arena_.rounded(spec.ws_bytes) > arena_.size()) {
         j.state = JobState::Failed;
@@ -130,6 +131,17 @@ void Scheduler::complete(uint64_t ticket, Job& j, int status) {
     ex_->retire(ticket, status);
 }
 
+void Scheduler::fail(uint64_t ticket, Job& j, int status) {
+    if (j.state != JobState::Admitted && j.state != JobState::Queued) return;
+    if (j.inflight > 0) {
+        // kernels of earlier ticks may still touch its buffers and workspace
+        if (!j.failing) j.fail_status = status;
+        j.failing = true;
+        return;
+    }
+    complete(ticket, j, status);
+}
+
 bool Scheduler::retire_ticks() {
     bool changed = false;
     for (size_t s = 0; s < slots_.size(); ++s) {
@@ -142,7 +154,12 @@ bool Scheduler::retire_ticks() {
             auto it = jobs_.find(c.first);
             if (it == jobs_.end()) continue;
             Job& j = it->second;
+            if (j.inflight > 0) --j.inflight;
             if (j.state != JobState::Admitted) continue;
+            if (j.failing) {
+                if (j.inflight == 0) complete(c.first, j, j.fail_status);
+                continue;
+            }
             for (int p = 0; p < 3; ++p) j.done[p] += c.second[p];
             if (finished(j)) complete(c.first, j, 0);
         }
@@ -153,16 +170,32 @@ bool Scheduler::retire_ticks() {
 
 bool Scheduler::admit_jobs() {
     bool changed = false;
-    while (!queue_.empty()) {
-        const uint64_t t = queue_.front();
+    const double now = ex_->now();
+    // The oldest queued job whose workspace does not fit blocks later
+    // workspace jobs only once it has waited max_wait_s; jobs that need no
+    // workspace always pass it.
+    bool blocked = false, blocked_aged = false;
+    for (auto it = queue_.begin(); it != queue_.end();) {
+        const uint64_t t = *it;
         Job& j = jobs_[t];
         size_t off = 0;
         if (j.spec.ws_bytes > 0) {
-            if (!arena_.alloc(j.spec.ws_bytes, &off)) break;  // first in, first admitted
+            if (blocked && blocked_aged) {
+                ++it;
+                continue;
+            }
+            if (!arena_.alloc(j.spec.ws_bytes, &off)) {
+                if (!blocked) {
+                    blocked = true;
+                    blocked_aged = now - j.t_submit > cfg_.max_wait_s;
+                }
+                ++it;
+                continue;
+            }
             j.has_ws = true;
             j.ws_offset = off;
         }
-        queue_.pop_front();
+        it = queue_.erase(it);
         changed = true;
         j.state = JobState::Admitted;
         active_.push_back(t);
@@ -187,6 +220,7 @@ bool Scheduler::build_tick(TickPlan* plan,
     std::vector<Cand> cands;
     for (uint64_t t : active_) {
         Job& j = jobs_[t];
+        if (j.failing) continue;
         int phase = -1;
         if (j.spec.segments <= 1) {
             if (j.issued[kFused] < total_items(j, kFused)) phase = kFused;
@@ -253,9 +287,13 @@ bool Scheduler::launch_ticks() {
         if (rc != 0) {
             for (auto& c : credits) {
                 auto it = jobs_.find(c.first);
-                if (it != jobs_.end()) complete(c.first, it->second, rc);
+                if (it != jobs_.end()) fail(c.first, it->second, rc);
             }
             continue;
+        }
+        for (auto& c : credits) {
+            auto it = jobs_.find(c.first);
+            if (it != jobs_.end()) ++it->second.inflight;
         }
         ++stats_.ticks;
         f.busy = true;

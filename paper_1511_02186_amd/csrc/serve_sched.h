@@ -45,6 +45,8 @@ struct JobSpec {
     int segments = 1;       // data segments (1: fused 64-query tiles)
     int64_t seg_len = 0;    // points per segment (== m when segments == 1)
     size_t ws_bytes = 0;    // device workspace held from admission to completion
+    double cost_scale = 1.0;  // device time per distance evaluation relative to the
+                              // FP32-scaled kernels (FP64 jobs are slower)
 };
 
 struct Item {
@@ -64,7 +66,9 @@ struct Config {
     size_t arena_bytes = 0;     // 0: no workspace can be admitted (fused jobs only)
     int slots = 2;              // ticks in flight (one stream each)
     double tick_pairs = 2e10;   // distance evaluations per tick (a soft quota)
-    double max_wait_s = 0.25;   // older jobs are served first, in arrival order
+    double max_wait_s = 0.25;   // older jobs are served first, in arrival order; a job
+                                // that waits for workspace longer than this stops
+                                // later workspace jobs from passing it
 };
 
 struct Stats {
@@ -95,6 +99,17 @@ class Scheduler {
 
     // Register a job.  Returns its ticket (> 0).  A job whose workspace can
     // never fit the arena fails at once (state Failed, status -2).
+    //
+    // Admission: queued jobs are admitted in arrival order while their
+    // workspace fits the arena.  A job that does not fit does not block the
+    // jobs behind it that need no workspace; jobs behind it that need
+    // workspace may pass it only until it has waited max_wait_s, after which
+    // the arena drains toward it.
+    //
+    // A job whose launch fails is reported Failed only once no tick that
+    // carries its items is still in flight, so that no kernel reads or writes
+    // its buffers, data set or workspace after the report; its workspace
+    // returns to the arena at the same moment.
     uint64_t submit(const JobSpec& spec);
     // State of a job; latency (seconds from submit to completion) and
     // status are set once it is Done or Failed.  Unknown tickets: false.
@@ -120,6 +135,9 @@ class Scheduler {
         int64_t issued[3] = {0, 0, 0};  // items issued per phase
         int64_t done[3] = {0, 0, 0};    // items completed per phase
         double remaining = 0.0;         // distance evaluations not yet issued
+        int inflight = 0;               // ticks in flight that carry its items
+        bool failing = false;           // failed; completes when inflight reaches 0
+        int fail_status = 0;
     };
     struct InFlight {
         bool busy = false;
@@ -131,6 +149,8 @@ class Scheduler {
     double item_cost(const Job& j, int phase) const;
     bool finished(const Job& j) const;
     void complete(uint64_t ticket, Job& j, int status);
+    // Fail the job now, or once its in-flight ticks have completed.
+    void fail(uint64_t ticket, Job& j, int status);
     bool retire_ticks();
     bool admit_jobs();
     bool launch_ticks();

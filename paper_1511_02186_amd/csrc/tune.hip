@@ -62,6 +62,7 @@ bool tuned_shape(const aidw_ctx* h, int64_t m, int64_t n, int k, aidw_tuning* ou
 extern "C" {
 
 aidw_status aidw_tune(aidw_t h, int64_t m, int64_t n, int k, double budget_s, aidw_tuning* best) {
+    ErrorScope es(h);
     if (!h) return fail(AIDW_EINVAL, "handle is NULL");
     if (m < 1 || n < 1 || m > INT32_MAX || n > INT32_MAX)
         return fail(AIDW_EINVAL, "need 1 <= m, n <= 2^31-1");
@@ -170,6 +171,7 @@ aidw_status aidw_tune(aidw_t h, int64_t m, int64_t n, int k, double budget_s, ai
 }
 
 aidw_status aidw_tune_save(aidw_t h, const char* path) {
+    ErrorScope es(h);
     if (!h || !path) return fail(AIDW_EINVAL, "handle or path is NULL");
     FILE* f = fopen(path, "w");
     if (!f) return fail(AIDW_EINVAL, "cannot write %s", path);
@@ -187,6 +189,7 @@ aidw_status aidw_tune_save(aidw_t h, const char* path) {
 }
 
 aidw_status aidw_tune_load(aidw_t h, const char* path) {
+    ErrorScope es(h);
     if (!h || !path) return fail(AIDW_EINVAL, "handle or path is NULL");
     FILE* f = fopen(path, "r");
     if (!f) return fail(AIDW_ENOTFOUND, "cannot read %s", path);

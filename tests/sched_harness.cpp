@@ -25,7 +25,9 @@ struct Fake : sv::Executor {
     double rate = 1e12;  // distance evaluations per fake second
     std::vector<double> finish;
     std::vector<bool> busy;
-    std::set<uint64_t> poison_admit, poison_launch;
+    std::set<uint64_t> poison_admit;
+    std::map<uint64_t, int> poison_launch;  // ticket -> launches that still succeed
+    std::map<uint64_t, int> launched;       // ticket -> successful launches so far
     std::vector<Launch> launches;
     std::map<uint64_t, int> retired;
     std::map<std::tuple<uint64_t, int, int, int>, int> issued;
@@ -33,8 +35,11 @@ struct Fake : sv::Executor {
     double now() override { return t; }
     int admit(uint64_t ticket, size_t) override { return poison_admit.count(ticket) ? -3 : 0; }
     int launch(const sv::TickPlan& plan, int slot) override {
-        for (uint64_t j : plan.jobs)
-            if (poison_launch.count(j)) return -3;
+        for (uint64_t j : plan.jobs) {
+            auto p = poison_launch.find(j);
+            if (p != poison_launch.end() && launched[j] >= p->second) return -3;
+        }
+        for (uint64_t j : plan.jobs) ++launched[j];
         Launch l{slot, t, t + plan.pair_evals / rate, plan.pair_evals, plan.jobs, plan.items};
         launches.push_back(l);
         finish[(size_t)slot] = l.finish;
@@ -90,12 +95,24 @@ uint64_t h_submit(void* p, int64_t m, int64_t n, int segments, int64_t seg_len, 
     return static_cast<Harness*>(p)->s->submit(s);
 }
 
+uint64_t h_submit_scaled(void* p, int64_t m, int64_t n, double cost_scale) {
+    sv::JobSpec s;
+    s.m = m;
+    s.n = n;
+    s.cost_scale = cost_scale;
+    return static_cast<Harness*>(p)->s->submit(s);
+}
+
 int h_step(void* p) { return static_cast<Harness*>(p)->s->step() ? 1 : 0; }
 int h_idle(void* p) { return static_cast<Harness*>(p)->s->idle() ? 1 : 0; }
 void h_advance(void* p, double dt) { static_cast<Harness*>(p)->ex.t += dt; }
 double h_now(void* p) { return static_cast<Harness*>(p)->ex.t; }
 void h_poison_admit(void* p, uint64_t t) { static_cast<Harness*>(p)->ex.poison_admit.insert(t); }
-void h_poison_launch(void* p, uint64_t t) { static_cast<Harness*>(p)->ex.poison_launch.insert(t); }
+void h_poison_launch(void* p, uint64_t t) { static_cast<Harness*>(p)->ex.poison_launch[t] = 0; }
+// Launches carrying job t fail once `ok` of them have succeeded.
+void h_poison_launch_after(void* p, uint64_t t, int ok) {
+    static_cast<Harness*>(p)->ex.poison_launch[t] = ok;
+}
 
 // state: 0 queued, 1 admitted, 2 done, 3 failed, -1 unknown
 int h_poll(void* p, uint64_t t, double* latency, int* status) {

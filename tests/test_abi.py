@@ -46,36 +46,83 @@ def test_binding_covers_every_declared_symbol():
         assert n in aidw._SIGNATURES, n
 
 
+def test_constants_match_header():
+    text = open(HEADER).read()
+    assert int(re.search(r"#define AIDW_KMAX (\d+)", text).group(1)) == aidw.AIDW_KMAX
+    assert int(re.search(r"#define AIDW_MAX_POINTS (\d+)LL", text).group(1)) == \
+        aidw.AIDW_MAX_POINTS
+    # the kernels' scan bounds j + 2 * 32 stay below 2^31
+    assert aidw.AIDW_MAX_POINTS + 64 < 2 ** 31
+
+
 def test_version_and_status_names():
     _lib_or_skip()
-    assert aidw.aidw_version() == (0 << 16) | 1
+    assert aidw.aidw_version() == (0 << 16) | 2
     assert aidw.status_name(aidw.AIDW_EINVAL) == "AIDW_EINVAL"
     assert aidw.status_name(aidw.AIDW_OK) == "AIDW_OK"
 
 
+STRUCTS = ["aidw_options", "aidw_problem", "aidw_tuning", "aidw_issue_costs",
+           "aidw_server_options", "aidw_job", "aidw_server_counters"]
+
+
+def _header_structs():
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    return sorted(set(re.findall(r"typedef\s+struct\s+(aidw_[a-z_]+)\s*\{", text)))
+
+
+def test_every_header_struct_is_mirrored():
+    assert _header_structs() == sorted(STRUCTS)
+
+
 def test_struct_layout_matches_header():
-    src = r"""
-#include <stddef.h>
-#include <stdio.h>
-#include "aidw.h"
-int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(aidw_problem),
-         offsetof(aidw_problem, m), offsetof(aidw_problem, k), offsetof(aidw_problem, alpha_levels),
-         offsetof(aidw_problem, area), offsetof(aidw_problem, out), offsetof(aidw_problem, knn_idx),
-         offsetof(aidw_problem, flags), sizeof(aidw_options), offsetof(aidw_options, hbm_budget_bytes),
-         offsetof(aidw_options, tune_path));
-  return 0;
-}
-"""
+    """sizeof and the offset of every field of every struct, C against ctypes."""
+    lines, want = [], []
+    for name in STRUCTS:
+        cls = getattr(aidw, name)
+        lines.append('printf("%%zu\\n", sizeof(%s));' % name)
+        want.append(ctypes.sizeof(cls))
+        for field, _ in cls._fields_:
+            lines.append('printf("%%zu\\n", offsetof(%s, %s));' % (name, field))
+            want.append(getattr(cls, field).offset)
+    src = ("#include <stddef.h>\n#include <stdio.h>\n#include \"aidw.h\"\nint main(void) {\n"
+           + "\n".join(lines) + "\nreturn 0;\n}\n")
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "layout.c")
         exe = os.path.join(d, "layout")
         open(c, "w").write(src)
-        subprocess.run(["gcc", "-I" + os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        subprocess.run(["gcc", "-Wall", "-I" + os.path.join(ROOT, "include"), c, "-o", exe],
+                       check=True)
         got = [int(v) for v in subprocess.run([exe], capture_output=True, text=True,
                                               check=True).stdout.split()]
-    P, O = aidw.aidw_problem, aidw.aidw_options
-    want = [ctypes.sizeof(P), P.m.offset, P.k.offset, P.alpha_levels.offset, P.area.offset,
-            P.out.offset, P.knn_idx.offset, P.flags.offset, ctypes.sizeof(O),
-            O.hbm_budget_bytes.offset, O.tune_path.offset]
     assert got == want
+
+
+def test_c_field_names_match_binding():
+    """Every field the header declares in a struct is in the ctypes mirror, in
+    the same order."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    for name in STRUCTS:
+        body = re.search(r"typedef\s+struct\s+%s\s*\{(.*?)\}\s*%s\s*;" % (name, name), text,
+                         flags=re.S).group(1)
+        fields = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            decl = re.sub(r"\[[^]]*\]", "", decl)
+            # "double R_min, R_max" declares two fields; "const void *a,*b" too
+            head, *rest = decl.split(",")
+            fields.append(re.findall(r"[A-Za-z_][A-Za-z_0-9]*", head)[-1])
+            fields += [re.findall(r"[A-Za-z_][A-Za-z_0-9]*", r)[-1] for r in rest]
+        assert fields == [f for f, _ in getattr(aidw, name)._fields_], name
+
+
+def test_last_error_takes_a_handle():
+    L = _lib_or_skip()
+    # no handle: the thread's most recent error of any call
+    h = ctypes.c_void_p()
+    opt = aidw.aidw_options(-7, 0, 0, None, 0)
+    st = L.aidw_create(ctypes.byref(h), ctypes.byref(opt))
+    assert st != aidw.AIDW_OK
+    assert aidw.last_error(None) != ""

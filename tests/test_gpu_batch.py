@@ -252,3 +252,39 @@ def test_split_with_alpha_zero_and_coincident_queries(ctx, torch):
         assert rel_err(out, o, scale).max() <= TOL_F32
         if levels[0] > 0:
             assert np.array_equal(out[:30], inst.data_z[:30])
+
+
+def test_deterministic_handle_ignores_launch_shape(ctx, torch):
+    """With aidw_options.deterministic the FP32-scaled result does not depend
+    on the launch shape (tuning, automatic split for few queries): it is the
+    unsplit one-query-per-lane kernel's, which is also what a batched launch
+    computes."""
+    inst = workloads.clustered(20000, 3000, 5, 10, on_point=0.02)  # few queries: auto split
+    dev = Dev(torch, inst)
+    det = aidw.Context(0, deterministic=1)
+    outs = []
+    try:
+        for t in [dict(), dict(q_per_lane=2), dict(q_per_lane=4, max_waves_per_simd=4),
+                  dict(split_segments=4), dict(q_per_lane=1, split_segments=1)]:
+            det.set_tuning(**t)
+            outs.append(det.interpolate(dev.data_xy, dev.data_z, dev.query_xy, inst.k,
+                                        inst.levels, inst.R_min, inst.R_max,
+                                        inst.area).cpu().numpy())
+        g = det.interpolate(dev.data_xy, dev.data_z, dev.query_xy, inst.k, inst.levels,
+                            inst.R_min, inst.R_max, inst.area,
+                            flags=aidw.AIDW_FLAG_GRID_KNN).cpu().numpy()
+    finally:
+        det.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    assert np.array_equal(outs[0], run_alone(ctx, torch, dev))
+    ctx.bind_current_stream()
+    aidw.check(aidw.aidw_interpolate_batch(ctx.h, [dev.problem(ctx)]))
+    torch.cuda.synchronize()
+    assert np.array_equal(dev.out.cpu().numpy(), outs[0])
+    # the automatic (non-deterministic) choice splits this problem: it agrees
+    # to rounding only
+    auto = ctx.interpolate(dev.data_xy, dev.data_z, dev.query_xy, inst.k, inst.levels,
+                           inst.R_min, inst.R_max, inst.area).cpu().numpy()
+    assert rel_err(auto, outs[0], np.abs(outs[0]) + 1e-30).max() <= 1e-6
+    assert rel_err(g, outs[0], np.abs(outs[0]) + 1e-30).max() <= 1e-6

@@ -484,7 +484,9 @@ def test_issue_cost_probe_is_plausible(ctx, torch):
 
 # ---- size limits and malformed pointers (host validation, nothing launched) ----------
 
-@pytest.mark.parametrize("field,value", [("m", 1 << 31), ("m", 0), ("n", 1 << 31), ("n", -1),
+@pytest.mark.parametrize("field,value", [("m", 1 << 31), ("m", aidw.AIDW_MAX_POINTS + 1),
+                                         ("m", 0), ("n", 1 << 31),
+                                         ("n", aidw.AIDW_MAX_POINTS + 1), ("n", -1),
                                          ("misaligned", 1), ("null_out", 0)])
 def test_size_limits_and_pointers_are_validated(ctx, torch, field, value):
     d = torch.rand(2, 64, device="cuda")

@@ -37,6 +37,9 @@ def lib():
     L.h_now.argtypes = [vp]
     L.h_poison_admit.argtypes = [vp, u64]
     L.h_poison_launch.argtypes = [vp, u64]
+    L.h_poison_launch_after.argtypes = [vp, u64, ctypes.c_int]
+    L.h_submit_scaled.restype = u64
+    L.h_submit_scaled.argtypes = [vp, i64, i64, dbl]
     L.h_poll.argtypes = [vp, u64, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int)]
     L.h_stats.argtypes = [vp, ctypes.POINTER(dbl)]
     L.h_launch.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(dbl),
@@ -56,6 +59,9 @@ class Sched:
 
     def submit(self, m, n, segments=1, seg_len=0, ws=0):
         return self.L.h_submit(self.h, m, n, segments, seg_len or m, float(ws))
+
+    def submit_scaled(self, m, n, cost_scale):
+        return self.L.h_submit_scaled(self.h, m, n, float(cost_scale))
 
     def step(self):
         return self.L.h_step(self.h)
@@ -125,13 +131,71 @@ def test_fifo_admission_under_workspace_budget(lib):
     s = Sched(lib, arena=1000, rate=1e9)
     a = s.submit(m=100000, n=64, segments=4, seg_len=25000, ws=600)
     b = s.submit(m=100000, n=64, segments=4, seg_len=25000, ws=600)
-    c = s.submit(m=100, n=64)  # needs no workspace but queues behind b
+    c = s.submit(m=100, n=64)  # needs no workspace: passes the blocked b
     s.step()
-    assert [s.poll(x)[0] for x in (a, b, c)] == [ADMITTED, QUEUED, QUEUED]
+    assert [s.poll(x)[0] for x in (a, b, c)] == [ADMITTED, QUEUED, ADMITTED]
     assert s.stats()["arena"] == 768  # 600 rounded up to 256-byte blocks
     s.run_until_idle()
     assert all(s.poll(x)[0] == DONE for x in (a, b, c))
     assert s.stats()["arena"] == 0
+    s.close()
+
+
+def test_blocked_head_is_passed_only_until_it_has_aged(lib):
+    # arena 1024: a holds 768; b (768) cannot fit; c (256) fits beside a
+    s = Sched(lib, arena=1024, max_wait=1.0, rate=1e3)
+    a = s.submit(m=100000, n=64, segments=4, seg_len=25000, ws=700)
+    b = s.submit(m=100000, n=64, segments=4, seg_len=25000, ws=700)
+    c = s.submit(m=100000, n=64, segments=4, seg_len=25000, ws=200)
+    s.step()
+    assert [s.poll(x)[0] for x in (a, b, c)] == [ADMITTED, QUEUED, ADMITTED]
+    # once b has waited longer than max_wait, a small workspace job stays
+    # behind it, while a job without workspace still passes
+    s.advance(1.5)
+    d = s.submit(m=100000, n=64, segments=4, seg_len=25000, ws=10)
+    e = s.submit(m=100, n=64)
+    s.step()
+    assert [s.poll(x)[0] for x in (b, d, e)] == [QUEUED, QUEUED, ADMITTED]
+    s.run_until_idle(dt=1.0)
+    assert all(s.poll(x)[0] == DONE for x in (a, b, c, d, e))
+    # d did not start before b
+    L = s.launches()
+    first = {t: min(i for i, x in enumerate(L) if t in x["jobs"]) for t in (b, d)}
+    assert first[b] <= first[d]
+    assert s.stats()["arena"] == 0
+    s.close()
+
+
+def test_cost_scale_weights_the_tick_quota(lib):
+    quota = 4 * 2 * 64 * 1000
+    s = Sched(lib, tick_pairs=quota, rate=1e9)
+    t = s.submit_scaled(m=1000, n=64 * 8, cost_scale=2.0)  # each item costs twice
+    s.run_until_idle()
+    assert [len(x["items"]) for x in s.launches()] == [2, 2, 2, 2]
+    assert s.poll(t)[0] == DONE
+    s.close()
+
+
+def test_failed_launch_completes_after_in_flight_ticks(lib):
+    # the job's first tick runs on slot 0; its second launch (slot 1) fails
+    # while the first is still in flight: the job is reported only after the
+    # first tick has finished, and its workspace is held until then
+    q = 64 * 1000
+    s = Sched(lib, arena=1 << 20, slots=2, tick_pairs=q, rate=1e3)
+    t = s.submit(m=4000, n=64 * 2, segments=4, seg_len=1000, ws=4096)
+    lib.h_poison_launch_after(s.h, t, 1)
+    s.step()
+    assert len(s.launches()) == 1
+    assert s.poll(t)[0] == ADMITTED and s.stats()["arena"] == 4096
+    s.advance(0.5 * q / 1e3)
+    s.step()
+    assert s.poll(t)[0] == ADMITTED and s.stats()["arena"] == 4096
+    s.advance(q / 1e3)
+    s.step()
+    state, _, status = s.poll(t)
+    assert state == FAILED and status == -3 and s.stats()["arena"] == 0
+    retired = ctypes.c_int()
+    assert lib.h_retired(s.h, t, ctypes.byref(retired)) == 1 and retired.value == -3
     s.close()
 
 
