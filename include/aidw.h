@@ -168,6 +168,29 @@ aidw_status aidw_interpolate(aidw_t h, const void* data_xy, const void* data_z, 
  * hipGraph; aidw_batch_* captures and replays launches. */
 aidw_status aidw_interpolate_ex(aidw_t h, const aidw_problem* p);
 
+/* For callers that cannot allocate device memory: code being captured into
+ * a hipGraph, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * problem, results and errors as aidw_interpolate_ex, but the call
+ * allocates nothing: no hipMalloc, hipFree or allocating library routine.
+ * The buffers the FP32-scaled kernels need beyond inputs and outputs (max |z|
+ * and the split-m partial lists and sums) live in a fixed device array of
+ * AIDW_NOALLOC_SCRATCH_BYTES per device, which the library holds from the
+ * first aidw_create on that device until the process ends (it is not
+ * counted against hbm_budget_bytes).  Every kernel writes the scratch it
+ * later reads within the same call, so no part of it must start at zero.
+ * When the automatic split of the data would need more scratch than that,
+ * the problem runs in as many segments as fit (down to the unsplit kernel,
+ * which needs 256 bytes), so its output can differ from
+ * aidw_interpolate_ex's in the last bits of the FP64 sums; when the split
+ * fits, the output is bit-identical.  A split forced by aidw_set_tuning that
+ * does not fit fails with AIDW_ENOMEM, and AIDW_FLAG_GRID_KNN with
+ * AIDW_EINVAL.  FP64 problems use no scratch.  All calls on one device
+ * share its array: calls that overlap on a device (several handles or
+ * streams, or AIDW_FLAG_ASYNC calls not yet finished on another stream)
+ * race, and must be serialised by the caller. */
+#define AIDW_NOALLOC_SCRATCH_BYTES (64ull << 20)
+aidw_status aidw_interpolate_noalloc(aidw_t h, const aidw_problem* p);
+
 /* Standard IDW (Sec. 2.1, Eq. 1): every query uses the constant power
  * `power` (finite, >= 0) over all m data points.  Fields of *p as in
  * aidw_interpolate_ex; its k, alpha_levels, R_min, R_max and area are

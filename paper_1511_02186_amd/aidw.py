@@ -36,6 +36,7 @@ AIDW_LAYOUT_SOA = 0
 AIDW_LAYOUT_AOAS = 1
 AIDW_KMAX = 32
 AIDW_MAX_POINTS = (1 << 31) - (1 << 16)
+AIDW_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class aidw_options(ctypes.Structure):
@@ -129,6 +130,7 @@ _SIGNATURES = {
                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_void_p]),
     "aidw_interpolate_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem)]),
+    "aidw_interpolate_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem)]),
     "aidw_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_tuning)]),
     "aidw_idw": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem), ctypes.c_double]),
     "aidw_interpolate_variant": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem),
@@ -236,6 +238,10 @@ def aidw_interpolate(h, data_xy_ptr, data_z_ptr, m, query_xy_ptr, n, k, alpha_le
 
 def aidw_interpolate_ex(h, problem: aidw_problem) -> int:
     return lib().aidw_interpolate_ex(h, ctypes.byref(problem))
+
+
+def aidw_interpolate_noalloc(h, problem: aidw_problem) -> int:
+    return lib().aidw_interpolate_noalloc(h, ctypes.byref(problem))
 
 
 def aidw_idw(h, problem: aidw_problem, power: float) -> int:

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <algorithm>
 #include <vector>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -325,12 +326,62 @@ hipError_t run_grid(aidw_t h, const aidw_problem* p, aidw_status* st_out) {
 }
 
 
+// Launch shape and data segments of an FP32-scaled full-scan problem.
+struct F32Plan {
+    aidw::LaunchF32 cfg;
+    aidw::SplitPlan sp;
+};
+
+F32Plan plan_f32(const aidw_ctx* h, const aidw_problem* p) {
+    aidw_tuning t = h->tuning;
+    aidw_tuning tuned;
+    if (h->deterministic)
+        t = aidw_tuning{1, 0, 1};  // the unsplit one-query-per-lane kernel
+    else if (!t.q_per_lane && !t.max_waves_per_simd && !t.split_segments &&
+             tuned_shape(h, p->m, p->n, p->k, &tuned))
+        t = tuned;
+    F32Plan pl{aidw::LaunchF32{t.q_per_lane ? t.q_per_lane : default_q_per_lane(h, p->n),
+                               t.max_waves_per_simd},
+               aidw::SplitPlan{1, (int)p->m, 0}};
+    if (!p->knn_idx) pl.sp = split_plan_for(h, t, p->m, p->n);
+    return pl;
+}
+
+// Workspace of an FP32-scaled problem: max |z| in the first slot, then the
+// split-m buffers.
+size_t f32_workspace_bytes(const F32Plan& pl, const aidw_problem* p) {
+    return kZmaxSlot +
+           (pl.sp.segments > 1 ? split_workspace_bytes(pl.sp, p->k, p->n, nullptr, nullptr) : 0);
+}
+
+// Queue the max-|z| reduction and the FP32-scaled kernels of plan pl, with
+// the workspace at w (f32_workspace_bytes(pl, p) bytes, 256-byte aligned).
+hipError_t launch_f32(aidw_t h, const aidw_problem* p, const F32Plan& pl, char* w) {
+    aidw::ProblemF32 q = problem_f32(p);
+    aidw::SplitWorkspace ws{};
+    if (pl.sp.segments > 1) split_workspace_bytes(pl.sp, p->k, p->n, &ws, w + kZmaxSlot);
+    float* zmax = reinterpret_cast<float*>(w);
+    q.zmax = zmax;
+    hipError_t e = aidw::launch_abs_max(q.dz, q.m, zmax, h->stream);
+    if (e == hipSuccess) e = aidw::launch_aidw_f32(q, pl.cfg, &pl.sp, &ws, h->stream);
+    return e;
+}
+
+// Report a failed launch, or wait for the work unless the call is asynchronous.
+aidw_status finish_launch(aidw_t h, const aidw_problem* p, hipError_t e) {
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    if (!(p->flags & AIDW_FLAG_ASYNC)) {
+        e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    }
+    return AIDW_OK;
+}
+
 aidw_status run_problem(aidw_t h, const aidw_problem* p) {
     aidw_status st = validate(p);
     if (st != AIDW_OK) return st;
     if (p->n == 0) return AIDW_OK;
     hipError_t e;
-    const int m = (int)p->m, n = (int)p->n;
     if (p->flags & AIDW_FLAG_GRID_KNN) {
         if (p->precision != AIDW_FP32_SCALED)
             return fail(AIDW_EINVAL, "AIDW_FLAG_GRID_KNN needs the FP32-scaled precision");
@@ -339,40 +390,68 @@ aidw_status run_problem(aidw_t h, const aidw_problem* p) {
         e = run_grid(h, p, &gst);
         if (gst != AIDW_OK) return gst;
     } else if (p->precision == AIDW_FP32_SCALED) {
-        aidw::ProblemF32 q = problem_f32(p);
-        aidw_tuning t = h->tuning;
-        aidw_tuning tuned;
-        if (h->deterministic)
-            t = aidw_tuning{1, 0, 1};  // the unsplit one-query-per-lane kernel
-        else if (!t.q_per_lane && !t.max_waves_per_simd && !t.split_segments &&
-                 tuned_shape(h, m, n, p->k, &tuned))
-            t = tuned;
-        aidw::LaunchF32 cfg{t.q_per_lane ? t.q_per_lane : default_q_per_lane(h, n),
-                            t.max_waves_per_simd};
-        aidw::SplitPlan sp{1, m, 0};
-        aidw::SplitWorkspace ws{};
-        if (!p->knn_idx) sp = split_plan_for(h, t, m, n);
-        // workspace: max |z| in the first slot, then the split-m buffers
-        const size_t need = kZmaxSlot + (sp.segments > 1
-                                             ? split_workspace_bytes(sp, p->k, n, nullptr, nullptr)
-                                             : 0);
-        aidw_status st = ensure_workspace(h, need);
+        const F32Plan pl = plan_f32(h, p);
+        st = ensure_workspace(h, f32_workspace_bytes(pl, p));
         if (st != AIDW_OK) return st;
-        char* w = static_cast<char*>(h->workspace);
-        if (sp.segments > 1) split_workspace_bytes(sp, p->k, n, &ws, w + kZmaxSlot);
-        float* zmax = reinterpret_cast<float*>(w);
-        q.zmax = zmax;
-        e = aidw::launch_abs_max(q.dz, m, zmax, h->stream);
-        if (e == hipSuccess) e = aidw::launch_aidw_f32(q, cfg, &sp, &ws, h->stream);
+        e = launch_f32(h, p, pl, static_cast<char*>(h->workspace));
     } else {
         e = aidw::launch_aidw_f64(problem_f64(p), h->stream);
     }
-    if (e != hipSuccess) return hip_fail(e, "kernel launch");
-    if (!(p->flags & AIDW_FLAG_ASYNC)) {
-        e = hipStreamSynchronize(h->stream);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return finish_launch(h, p, e);
+}
+
+}  // namespace
+
+// ---- Device scratch of the allocation-free entry point ----------------------
+// aidw_interpolate_noalloc keeps max |z| and the split-m buffers here instead
+// of in the handle's workspace.  Every device the library runs on holds its
+// own copy until the process ends.  On the host the array's name is not a
+// device address: host code uses only the per-device address that
+// hipGetSymbolAddress returns (looked up in aidw_create).
+static __device__ __align__(256) unsigned char scratch[AIDW_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // this device's copy of `scratch`, once looked up
+
+// The address of `scratch` on `device`, which must be the current device.
+aidw_status noalloc_scratch(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices)
+        return fail(AIDW_EINVAL, "device %d beyond the %d the library tracks", device, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(AIDW_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[device] = ptr;
     }
+    *out = g_scratch_ptr[device];
     return AIDW_OK;
+}
+
+// The most data segments (at most sp.segments) whose split workspace, after
+// the max-|z| slot, fits in `cap` bytes; one segment (the fused kernel,
+// which needs only the slot) when not even two fit.
+aidw::SplitPlan fit_split(aidw::SplitPlan sp, int k, int64_t n, int64_t m, size_t cap) {
+    auto need = [&](const aidw::SplitPlan& s) {
+        return kZmaxSlot + split_workspace_bytes(s, k, n, nullptr, nullptr);
+    };
+    if (sp.segments <= 1 || need(sp) <= cap) return sp;
+    const size_t fixed = kZmaxSlot + 4 * sizeof(float) * (size_t)n + 512;
+    const size_t per_segment = (size_t)k * n * sizeof(float) + 2 * sizeof(double) * (size_t)n;
+    int64_t want = cap > fixed ? (int64_t)((cap - fixed) / per_segment) : 0;
+    want = std::min<int64_t>(want, sp.segments - 1);
+    for (; want >= 2; --want) {
+        int64_t seg = (m + want - 1) / want;
+        seg = (seg + 31) / 32 * 32;  // whole scalar-load batches
+        aidw::SplitPlan t{(int)((m + seg - 1) / seg), (int)seg, sp.tiles};
+        if (t.segments > 1 && need(t) <= cap) return t;
+    }
+    return aidw::SplitPlan{1, (int)m, sp.tiles};
 }
 
 }  // namespace
@@ -399,6 +478,11 @@ aidw_status aidw_create(aidw_t* out, const aidw_options* opt) {
     h->default_precision = o.default_precision;
     h->deterministic = o.deterministic != 0;
     h->hbm_budget = o.hbm_budget_bytes;
+    const aidw_status sst = noalloc_scratch(o.device, &h->scratch);
+    if (sst != AIDW_OK) {
+        delete h;
+        return sst;
+    }
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, o.device) == hipSuccess)
         h->cu_count = cus;
@@ -465,6 +549,36 @@ aidw_status aidw_interpolate_ex(aidw_t h, const aidw_problem* p) {
     ErrorScope es(h);
     if (!h) return fail(AIDW_EINVAL, "handle is NULL");
     return run_problem(h, p);
+}
+
+aidw_status aidw_interpolate_noalloc(aidw_t h, const aidw_problem* p) {
+    ErrorScope es(h);
+    if (!h) return fail(AIDW_EINVAL, "handle is NULL");
+    aidw_status st = validate(p);
+    if (st != AIDW_OK) return st;
+    if (p->flags & AIDW_FLAG_GRID_KNN)
+        return fail(AIDW_EINVAL, "AIDW_FLAG_GRID_KNN needs the handle's workspace "
+                                 "(aidw_interpolate_ex)");
+    if (p->n == 0) return AIDW_OK;
+    hipError_t e;
+    if (p->precision == AIDW_FP64) {
+        e = aidw::launch_aidw_f64(problem_f64(p), h->stream);  // uses no scratch
+    } else {
+        F32Plan pl = plan_f32(h, p);
+        const size_t cap = AIDW_NOALLOC_SCRATCH_BYTES;
+        if (f32_workspace_bytes(pl, p) > cap) {
+            if (h->tuning.split_segments > 1)
+                return fail(AIDW_ENOMEM,
+                            "split into %d segments the problem needs %zu bytes of scratch, "
+                            "more than the %zu of the allocation-free entry point",
+                            pl.sp.segments, f32_workspace_bytes(pl, p), cap);
+            pl.sp = fit_split(pl.sp, p->k, p->n, p->m, cap);
+        }
+        if (f32_workspace_bytes(pl, p) > cap)  // unreachable: one segment needs 256 bytes
+            return fail(AIDW_ENOMEM, "scratch of %zu bytes exceeded", cap);
+        e = launch_f32(h, p, pl, static_cast<char*>(h->scratch));
+    }
+    return finish_launch(h, p, e);
 }
 
 aidw_status aidw_idw(aidw_t h, const aidw_problem* p, double power) {

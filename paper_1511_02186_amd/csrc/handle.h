@@ -41,6 +41,7 @@ struct aidw_ctx {
     aidw_tuning tuning{0, 0, 0};  // zero fields: automatic
     void* workspace = nullptr;    // split-m scratch, grown on demand
     size_t workspace_bytes = 0;
+    void* scratch = nullptr;      // this device's fixed scratch (aidw_interpolate_noalloc)
     // Registered data sets; the mutex also guards hbm_in_use, which servers
     // running on their own threads update.
     std::mutex mu;
