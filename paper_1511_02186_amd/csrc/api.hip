@@ -255,13 +255,28 @@ size_t split_workspace_bytes(const aidw::SplitPlan& sp, int k, int64_t n, aidw::
     return o_psum + psum;
 }
 
+// Problems of fewer data points than this keep the two passes: the single
+// pass gains little there.
+constexpr int64_t kSpecMinPoints = 1024;
+
 aidw::ProblemF32 problem_f32(const aidw_problem* p) {
     const int m = (int)p->m, n = (int)p->n;
     const float* xy = static_cast<const float*>(p->data_xy);
     const float* qxy = static_cast<const float*>(p->query_xy);
-    return aidw::ProblemF32{xy, xy + m, static_cast<const float*>(p->data_z), qxy, qxy + n,
-                            static_cast<float*>(p->out), p->r_obs, p->alpha, p->knn_idx, m, n,
-                            alpha_params(p)};
+    aidw::ProblemF32 q{xy, xy + m, static_cast<const float*>(p->data_z), qxy, qxy + n,
+                       static_cast<float*>(p->out), p->r_obs, p->alpha, p->knn_idx, m, n,
+                       alpha_params(p)};
+    // The speculative single pass assumes alpha = alpha_5, which Eq. 6 gives
+    // for mu_R >= 0.9; it is worth it only when that power is whole (one
+    // transcendental per pair).  Eq. 5 reaches mu = 0.9 at
+    // R_min + acos(-0.8) R_max / pi (or at R_max, if that comes first).
+    const double a5 = p->alpha_levels[4];
+    if (a5 >= 1.0 && a5 <= 8.0 && a5 == std::floor(a5) && p->m >= kSpecMinPoints) {
+        q.spec_power = (int)a5;
+        const double R90 = std::min(p->R_max, p->R_min + std::acos(-0.8) * p->R_max / M_PI);
+        q.spec_dist_sum = (float)(p->k * R90 * q.ap.r_exp * (1.0 - 1e-4));
+    }
+    return q;
 }
 
 aidw::ProblemF64 problem_f64(const aidw_problem* p) {
@@ -330,7 +345,12 @@ hipError_t run_grid(aidw_t h, const aidw_problem* p, aidw_status* st_out) {
 struct F32Plan {
     aidw::LaunchF32 cfg;
     aidw::SplitPlan sp;
+    bool spec;  // the speculative single pass, with pass 2 deferred for failed tiles
 };
+
+// Waves in one round of the device (8 per SIMD, 4 SIMDs per CU): what the
+// deferred pass 2 of the speculative launch aims to fill.
+int round_waves(const aidw_ctx* h) { return (h->cu_count > 0 ? h->cu_count : 256) * 4 * 8; }
 
 F32Plan plan_f32(const aidw_ctx* h, const aidw_problem* p) {
     aidw_tuning t = h->tuning;
@@ -342,22 +362,37 @@ F32Plan plan_f32(const aidw_ctx* h, const aidw_problem* p) {
         t = tuned;
     F32Plan pl{aidw::LaunchF32{t.q_per_lane ? t.q_per_lane : default_q_per_lane(h, p->n),
                                t.max_waves_per_simd},
-               aidw::SplitPlan{1, (int)p->m, 0}};
+               aidw::SplitPlan{1, (int)p->m, 0}, false};
     if (!p->knn_idx) pl.sp = split_plan_for(h, t, p->m, p->n);
+    // The speculative single pass replaces the unsplit one-query-per-lane
+    // kernel when alpha_5 is a whole power; it is off in deterministic mode,
+    // which promises the kernel batched launches use.
+    pl.spec = !h->deterministic && !p->knn_idx && pl.sp.segments == 1 && pl.cfg.q_per_lane == 1 &&
+              pl.cfg.max_waves_per_simd == 0 && problem_f32(p).spec_power != 0;
     return pl;
 }
 
 // Workspace of an FP32-scaled problem: max |z| in the first slot, then the
 // split-m buffers.
-size_t f32_workspace_bytes(const F32Plan& pl, const aidw_problem* p) {
+size_t f32_workspace_bytes(const aidw_ctx* h, const F32Plan& pl, const aidw_problem* p) {
+    if (pl.spec) return kZmaxSlot + aidw::spec_workspace_bytes(p->n, round_waves(h), nullptr, nullptr);
     return kZmaxSlot +
            (pl.sp.segments > 1 ? split_workspace_bytes(pl.sp, p->k, p->n, nullptr, nullptr) : 0);
 }
 
 // Queue the max-|z| reduction and the FP32-scaled kernels of plan pl, with
-// the workspace at w (f32_workspace_bytes(pl, p) bytes, 256-byte aligned).
+// the workspace at w (f32_workspace_bytes(h, pl, p) bytes, 256-byte aligned).
 hipError_t launch_f32(aidw_t h, const aidw_problem* p, const F32Plan& pl, char* w) {
     aidw::ProblemF32 q = problem_f32(p);
+    if (pl.spec) {
+        aidw::DeferWorkspace dw{};
+        aidw::spec_workspace_bytes(p->n, round_waves(h), &dw, w + kZmaxSlot);
+        float* zmax = reinterpret_cast<float*>(w);
+        q.zmax = zmax;
+        hipError_t e = aidw::launch_abs_max(q.dz, q.m, zmax, h->stream, dw.count);
+        if (e == hipSuccess) e = aidw::launch_aidw_f32_spec(q, dw, h->stream);
+        return e;
+    }
     aidw::SplitWorkspace ws{};
     if (pl.sp.segments > 1) split_workspace_bytes(pl.sp, p->k, p->n, &ws, w + kZmaxSlot);
     float* zmax = reinterpret_cast<float*>(w);
@@ -391,7 +426,7 @@ aidw_status run_problem(aidw_t h, const aidw_problem* p) {
         if (gst != AIDW_OK) return gst;
     } else if (p->precision == AIDW_FP32_SCALED) {
         const F32Plan pl = plan_f32(h, p);
-        st = ensure_workspace(h, f32_workspace_bytes(pl, p));
+        st = ensure_workspace(h, f32_workspace_bytes(h, pl, p));
         if (st != AIDW_OK) return st;
         e = launch_f32(h, p, pl, static_cast<char*>(h->workspace));
     } else {
@@ -566,15 +601,16 @@ aidw_status aidw_interpolate_noalloc(aidw_t h, const aidw_problem* p) {
     } else {
         F32Plan pl = plan_f32(h, p);
         const size_t cap = AIDW_NOALLOC_SCRATCH_BYTES;
-        if (f32_workspace_bytes(pl, p) > cap) {
+        if (pl.spec && f32_workspace_bytes(h, pl, p) > cap) pl.spec = false;
+        if (f32_workspace_bytes(h, pl, p) > cap) {
             if (h->tuning.split_segments > 1)
                 return fail(AIDW_ENOMEM,
                             "split into %d segments the problem needs %zu bytes of scratch, "
                             "more than the %zu of the allocation-free entry point",
-                            pl.sp.segments, f32_workspace_bytes(pl, p), cap);
+                            pl.sp.segments, f32_workspace_bytes(h, pl, p), cap);
             pl.sp = fit_split(pl.sp, p->k, p->n, p->m, cap);
         }
-        if (f32_workspace_bytes(pl, p) > cap)  // unreachable: one segment needs 256 bytes
+        if (f32_workspace_bytes(h, pl, p) > cap)  // unreachable: one segment needs 256 bytes
             return fail(AIDW_ENOMEM, "scratch of %zu bytes exceeded", cap);
         e = launch_f32(h, p, pl, static_cast<char*>(h->scratch));
     }

@@ -39,6 +39,12 @@ struct ProblemF32 {
     // optional: max |z| over the data (written by launch_abs_max before the
     // pass-2 kernels); lets whole-power waves skip the d_min rescaling
     const float* zmax;
+    // Speculative single pass (set by the host): the whole power alpha_5 that
+    // pass 1 may form the pass-2 sums for (0: none), and the sum of the k
+    // neighbour distances below which a query no longer reaches that power's
+    // range (mu_R >= 0.9 in Eq. 5), used to stop speculating early.
+    int spec_power;
+    float spec_dist_sum;
 };
 
 struct ProblemF64 {
@@ -85,6 +91,17 @@ struct SplitWorkspace {
     float* qpar;   // [4][n] per query: -alpha/2, (alpha/2) log2 d_min^2, d_min,
                    // and the whole power of the one-transcendental pass 2 (0: none)
     double* psum;  // [segments][2][n] per-segment sum w and sum w z
+};
+
+// Workspace of the speculative single-pass launch (spec_workspace_bytes):
+// tiles whose speculation fails leave their pass-2 terms in qpar and their
+// index in list, and the deferred pass 2 runs them in data segments.
+struct DeferWorkspace {
+    int* count;    // tiles listed (zeroed by the max-|z| kernel before the scan)
+    int* list;     // [tiles] tile indices, in no particular order
+    float* qpar;   // [4][n] as SplitWorkspace::qpar, for listed tiles only
+    double* psum;  // [segments][2][count * 64] per-segment sums of listed tiles
+    int target;    // waves the deferred pass 2 aims for (one round of the chip)
 };
 
 // One unit of batched work: 64 consecutive queries of one problem.
@@ -172,7 +189,8 @@ struct GridWorkspace {
 };
 
 // max |z_i| over m values into *out (one workgroup; NaN wins, inf is kept).
-hipError_t launch_abs_max(const float* z, int m, float* out, hipStream_t s);
+// Also zeroes *clear when it is not null.
+hipError_t launch_abs_max(const float* z, int m, float* out, hipStream_t s, int* clear = nullptr);
 // The same for many arrays, one workgroup per task.
 hipError_t launch_abs_max_tasks(const AbsMaxTask* tasks, int count, hipStream_t s);
 
@@ -187,6 +205,13 @@ hipError_t launch_aidw_f32_pass2(const ProblemF32& p, SplitPlan sp, const float*
 
 hipError_t launch_aidw_f32(const ProblemF32& p, const LaunchF32& cfg, const SplitPlan* sp,
                            const SplitWorkspace* ws, hipStream_t stream);
+// The speculative single pass (p.spec_power != 0, one query per lane), then
+// pass 2 of the tiles whose speculation failed.  p.zmax must have been written
+// and *ws.count zeroed before (launch_abs_max with clear = ws.count).
+hipError_t launch_aidw_f32_spec(const ProblemF32& p, const DeferWorkspace& ws, hipStream_t stream);
+// Bytes of DeferWorkspace for n queries; with ws/base given, also lays it out
+// at base (256-byte aligned).
+size_t spec_workspace_bytes(int64_t n, int target, DeferWorkspace* ws, char* base);
 hipError_t launch_aidw_f32_batch(const BatchLaunch& b, hipStream_t stream);
 hipError_t launch_aidw_f64(const ProblemF64& p, hipStream_t stream);
 // Data-access variants (0 scalar, 1 LDS tiles, 2 per-lane loads) x layouts

@@ -34,23 +34,25 @@ __device__ __forceinline__ double eq6_alpha(double mu, const double* lv) {
 template <int K, typename T>
 __device__ __forceinline__ double alpha_from_list(const T (&t)[K], const AlphaParams& ap,
                                                   double& r_obs) {
-    const int pad = K - ap.k;
+    // The K - k padding entries are -inf and every real entry is >= 0 (or
+    // +inf): testing the value instead of the index keeps the test per lane,
+    // so no uniform masks of the padding stay live in SGPRs through the scan.
     double s = 0.0;
 #pragma unroll
     for (int i = 0; i < K; ++i)
-        if (i >= pad) s += sqrt((double)t[i]);
+        if (t[i] > (T)-INFINITY) s += sqrt((double)t[i]);
     r_obs = s / (double)ap.k;
     const double R = r_obs / ap.r_exp;
     return eq6_alpha(eq5_mu(R, ap.R_min, ap.R_max), ap.levels);
 }
 
-// The smallest real entry (index K - k) read with static indices only.
+// The smallest real entry (index K - k: the first that is not -inf padding),
+// read with static indices only.
 template <int K, typename T>
-__device__ __forceinline__ T list_min(const T (&t)[K], int k) {
-    const int pad = K - k;
+__device__ __forceinline__ T list_min(const T (&t)[K], int) {
     T v = t[K - 1];
 #pragma unroll
-    for (int i = 0; i < K; ++i) v = (i == pad) ? t[i] : v;
+    for (int i = K - 1; i >= 0; --i) v = t[i] > (T)-INFINITY ? t[i] : v;
     return v;
 }
 

@@ -437,6 +437,100 @@ __device__ __forceinline__ bool unscaled_ok(float aL0, const float* zmax) {
     return aL0 <= 60.0f && -aL0 <= lim;
 }
 
+// ---- speculative single pass -------------------------------------------------
+// Pass 1 together with the pass-2 sums of one whole power A, from the same
+// squared distances.  When alpha_5 is a whole number A in [1, 8], alpha is A
+// for every query whose R reaches R_max (Eq. 5 gives mu_R = 1 and Eq. 6
+// alpha_5); on uniform data that is nearly every query, because the mean of
+// k neighbour distances exceeds the expected first-neighbour distance of
+// Eq. 2 several times.  A wave whose 64 queries all end at alpha = A, with
+// unscaled weights allowed, has then finished both passes in one scan; the
+// others run pass 2 as usual.  The sums are those of pass 2's unscaled
+// whole-power loop bit for bit: the same batches aligned at j0, the same
+// order and the same rounding (scan_wsum_int<A, false>), so the result does
+// not depend on whether the speculation held.  The k-nearest list comes out
+// as pass 1's: the multiset of the k smallest squared distances does not
+// depend on the batching.
+template <int K, int A>
+__device__ __forceinline__ void scan_knn_wsum_int(cptr X, cptr Y, cptr Z, int j0, int j1, float qx,
+                                                  float qy, float (&top)[K], double& Sw,
+                                                  double& Swz) {
+#pragma clang fp contract(off)
+    constexpr int B = batch2_for<1>();
+    // One batch: B squared distances, the list screen and insertion, then
+    // the B rsq in one burst (the first result is ready before the burst
+    // ends, so the weights wait on nothing) and the weights and sums.  The
+    // distances turn into their rsq in place: a batch needs B registers.
+    // The z of a batch are loaded after its distances (so x, y and z are
+    // never in SGPRs together) and arrive during the rsq burst.
+    int j = j0;
+    for (; j + B <= j1; j += B) {
+        float v[B];
+        {
+            float px[B], py[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                px[u] = X[j + u];
+                py[u] = Y[j + u];
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) v[u] = sqdist(qx, qy, px[u], py[u]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        float pz[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) pz[u] = Z[j + u];
+        __builtin_amdgcn_sched_barrier(0);
+        float mn = v[0];
+#pragma unroll
+        for (int u = 1; u < B; ++u) mn = fminf(mn, v[u]);
+        if (mn < top[K - 1]) {
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                if (v[u] < top[K - 1]) list_insert<K>(top, v[u]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < B; ++u) v[u] = __builtin_amdgcn_rsqf(v[u]);
+        __builtin_amdgcn_sched_barrier(0);
+        int_batch<A, false>(v, pz, 0.0f, Sw, Swz);
+    }
+    for (; j < j1; ++j) {
+        const float d2 = sqdist(qx, qy, X[j], Y[j]);
+        if (d2 < top[K - 1]) list_insert<K>(top, d2);
+        const float w = ipow<A>(__builtin_amdgcn_rsqf(d2));
+        Sw += (double)w;
+        Swz += (double)(w * Z[j]);
+    }
+}
+
+// Pass 1 with speculative sums for power A over a prefix of the points.
+// After the first eighth of the points the wave checks that in every lane
+// the k neighbour distances found so far still sum to at least
+// p.spec_dist_sum, i.e. that R is still in the range where Eq. 6 gives
+// alpha_5 (R only falls as points are added, so a lane below it seldom comes
+// back); if so the speculation goes on to the end, else it stops there.
+// Returns the first point that pass 1 has not seen: m when the sums in Sw,
+// Swz cover every point, else where the plain scan must continue.
+template <int K, int A>
+__device__ __forceinline__ int knn_speculative(const ProblemF32& p, float qx, float qy,
+                                               float (&top)[K], double& Sw, double& Swz) {
+    cptr X = as_const(p.dx), Y = as_const(p.dy), Z = as_const(p.dz);
+    const int jc = (p.m / 8) & ~(batch2_for<1>() - 1);
+    int j0 = 0, j1 = jc;
+    for (;;) {
+        scan_knn_wsum_int<K, A>(X, Y, Z, j0, j1, qx, qy, top, Sw, Swz);
+        if (j1 == p.m) return p.m;
+        float s = 0.0f;  // -inf padding entries add nothing
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (top[i] > -INFINITY) s += __builtin_sqrtf(top[i]);
+        if (!__all(s >= p.spec_dist_sum)) return j1;
+        j0 = j1;
+        j1 = p.m;
+    }
+}
+
 template <int A>
 __device__ __forceinline__ void scan_wsum_int_any(cptr X, cptr Y, cptr Z, int j0, int j1,
                                                   float qx, float qy, float dmin, bool unscaled,
@@ -501,8 +595,56 @@ __device__ __forceinline__ void load_queries(const ProblemF32& p, int base, int 
 }
 
 // ---- one tile of 64*Q queries, both passes over all m points ---------------
+// The alpha parameters of a problem, read through this pointer only after
+// pass 1 (see fused_tile).
+typedef const __attribute__((address_space(4))) AlphaParams* alpha_ptr;
+
+__device__ __forceinline__ AlphaParams load_alpha(alpha_ptr a) {
+    AlphaParams ap;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) ap.levels[j] = a->levels[j];
+    ap.R_min = a->R_min;
+    ap.R_max = a->R_max;
+    ap.r_exp = a->r_exp;
+    ap.k = a->k;
+    return ap;
+}
+
+// Pass-1 result of one lane's queries: the pass-2 terms (Eq. 2-6) and the
+// diagnostic outputs.  The alpha parameters (app points at p.ap) are read only
+// here, through an address laundered by an empty asm: loads of kernel
+// arguments otherwise all go to the kernel's entry, and these 17 SGPRs would
+// stay live through pass 1, which costs resident waves (on gfx950 8 per SIMD
+// up to 80 SGPRs, 7 up to about 88, 6 beyond).
 template <int K, int Q, bool TRACK>
-__device__ __forceinline__ void fused_tile(const ProblemF32& p, int base) {
+__device__ __forceinline__ void tile_powers(const ProblemF32& p, alpha_ptr app, const int (&qi)[Q],
+                                            const float (&top)[Q][K],
+                                            const int (&tix)[TRACK ? Q : 1][TRACK ? K : 1],
+                                            float (&na)[Q], float (&aL0)[Q], float (&d2min)[Q],
+                                            int& ipw) {
+    asm volatile("" : "+s"(app));
+    const AlphaParams ap = load_alpha(app);
+    const int pad = K - ap.k;
+    ipw = 0;
+#pragma unroll
+    for (int s = 0; s < Q; ++s) {
+        double r_obs, al;
+        query_power<K>(top[s], ap, r_obs, al, na[s], aL0[s], d2min[s]);
+        if (Q == 1) ipw = integer_power(al, d2min[s]);
+        if (qi[s] < p.n) {
+            if (p.r_obs) p.r_obs[qi[s]] = r_obs;
+            if (p.alpha) p.alpha[qi[s]] = al;
+            if constexpr (TRACK) {
+#pragma unroll
+                for (int i = 0; i < K; ++i)
+                    if (i >= pad) p.knn[(int64_t)qi[s] * ap.k + (i - pad)] = tix[s][i];
+            }
+        }
+    }
+}
+
+template <int K, int Q, bool TRACK>
+__device__ __forceinline__ void fused_tile(const ProblemF32& p, alpha_ptr app, int base) {
     int qi[Q];
     float qx[Q], qy[Q];
     load_queries<Q>(p, base, qi, qx, qy);
@@ -512,24 +654,9 @@ __device__ __forceinline__ void fused_tile(const ProblemF32& p, int base) {
     init_lists<K, Q, TRACK>(top, tix, p.ap.k);
     scan_knn<K, Q, TRACK>(as_const(p.dx), as_const(p.dy), 0, p.m, qx, qy, top, tix);
 
-    const int pad = K - p.ap.k;
     float na[Q], aL0[Q], d2min[Q];
-    int ipw = 0;
-#pragma unroll
-    for (int s = 0; s < Q; ++s) {
-        double r_obs, al;
-        query_power<K>(top[s], p.ap, r_obs, al, na[s], aL0[s], d2min[s]);
-        if (Q == 1) ipw = integer_power(al, d2min[s]);
-        if (qi[s] < p.n) {
-            if (p.r_obs) p.r_obs[qi[s]] = r_obs;
-            if (p.alpha) p.alpha[qi[s]] = al;
-            if constexpr (TRACK) {
-#pragma unroll
-                for (int i = 0; i < K; ++i)
-                    if (i >= pad) p.knn[(int64_t)qi[s] * p.ap.k + (i - pad)] = tix[s][i];
-            }
-        }
-    }
+    int ipw;
+    tile_powers<K, Q, TRACK>(p, app, qi, top, tix, na, aL0, d2min, ipw);
 
     double Sw[Q], Swz[Q];
 #pragma unroll
@@ -542,9 +669,72 @@ __device__ __forceinline__ void fused_tile(const ProblemF32& p, int base) {
         if (qi[s] < p.n) p.out[qi[s]] = (float)(Swz[s] / Sw[s]);
 }
 
+// One tile of the speculative launch: pass 1 with the sums of p.spec_power
+// (knn_speculative), and the output where the speculation held in every lane;
+// otherwise the tile's pass-2 terms go to ws.qpar and its index to ws.list,
+// for the deferred pass 2.  Keeping pass 2 out of this kernel keeps it under
+// 80 SGPRs (8 waves per SIMD), and a failed tile's pass 2, split into data
+// segments, runs spread over the chip instead of as one long wave at the end.
+template <int K>
+__device__ __forceinline__ void spec_tile(const ProblemF32& p, alpha_ptr app, int tile,
+                                          const DeferWorkspace& ws) {
+    int qi[1];
+    float qx[1], qy[1];
+    load_queries<1>(p, tile * kWaveSize, qi, qx, qy);
+    float top[1][K];
+    int tix[1][1];
+    init_lists<K, 1, false>(top, tix, p.ap.k);
+    double Sw = 0.0, Swz = 0.0;
+    int spec = 0;   // the power whose sums cover every point, or 0
+    int jscan = 0;  // where the plain pass 1 continues
+    switch (p.spec_power) {
+#define AIDW_SPEC_CASE(A)                                                    \
+    case A:                                                                  \
+        jscan = knn_speculative<K, A>(p, qx[0], qy[0], top[0], Sw, Swz);      \
+        spec = jscan == p.m ? A : 0;                                         \
+        break;
+        AIDW_SPEC_CASE(1) AIDW_SPEC_CASE(2) AIDW_SPEC_CASE(3) AIDW_SPEC_CASE(4)
+        AIDW_SPEC_CASE(5) AIDW_SPEC_CASE(6) AIDW_SPEC_CASE(7) AIDW_SPEC_CASE(8)
+#undef AIDW_SPEC_CASE
+        default:
+            break;
+    }
+    scan_knn<K, 1, false>(as_const(p.dx), as_const(p.dy), jscan, p.m, qx, qy, top, tix);
+
+    float na[1], aL0[1], d2min[1];
+    int ipw;
+    tile_powers<K, 1, false>(p, app, qi, top, tix, na, aL0, d2min, ipw);
+    // the sums stand when pass 2 would take the unscaled loop of that same
+    // power in this wave (the choice scan_wsum_any makes)
+    if (spec != 0 && __all(ipw == spec) && __all(unscaled_ok(aL0[0], p.zmax))) {
+        if (qi[0] < p.n) p.out[qi[0]] = (float)(Swz / Sw);
+        return;
+    }
+    if (qi[0] < p.n) {
+        ws.qpar[qi[0]] = na[0];
+        ws.qpar[p.n + qi[0]] = aL0[0];
+        ws.qpar[2 * p.n + qi[0]] = sqrtf(d2min[0]);
+        ws.qpar[3 * p.n + qi[0]] = (float)ipw;
+    }
+    if (lane_id() == 0) ws.list[atomicAdd(ws.count, 1)] = tile;
+}
+
 template <int K, int Q, bool TRACK>
 __global__ __launch_bounds__(kGroupSize) void aidw_f32_fused(ProblemF32 p) {
-    fused_tile<K, Q, TRACK>(p, wave_id() * Q * kWaveSize);
+    // p is the kernel's only explicit argument: it starts the kernarg segment
+    const ProblemF32 __attribute__((address_space(4)))* kp =
+        (const ProblemF32 __attribute__((address_space(4)))*)__builtin_amdgcn_kernarg_segment_ptr();
+    fused_tile<K, Q, TRACK>(p, &kp->ap, wave_id() * Q * kWaveSize);
+}
+
+// The speculative launch: one wave per tile (see spec_tile).
+template <int K>
+__global__ __launch_bounds__(kGroupSize) void aidw_f32_fused_spec(ProblemF32 p, DeferWorkspace ws) {
+    const ProblemF32 __attribute__((address_space(4)))* kp =
+        (const ProblemF32 __attribute__((address_space(4)))*)__builtin_amdgcn_kernarg_segment_ptr();
+    const int tile = wave_id();
+    if (tile * kWaveSize >= p.n) return;
+    spec_tile<K>(p, &kp->ap, tile, ws);
 }
 
 // ---- batched: one wave per (problem, tile) item -------------------------------
@@ -555,7 +745,7 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_batch(const ProblemF32* _
     const int it = wave_id();
     if (it >= n_items) return;
     const BatchItem w = items[it];
-    fused_tile<K, 1, false>(probs[w.problem], w.base);
+    fused_tile<K, 1, false>(probs[w.problem], (alpha_ptr)&probs[w.problem].ap, w.base);
 }
 
 // Per-segment k-nearest lists keep only the k real entries of each list,
@@ -673,6 +863,70 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_wsum_reduce(ProblemF32 p,
 }
 
 
+// ---- deferred pass 2 of the tiles whose speculation failed ------------------
+// `count` tiles (only known on the device) run as (tile, data segment) items,
+// S segments each with S chosen so that count * S is about ws.target waves
+// (one round of the chip): a few failed tiles then still fill the device.
+// Segments are whole 16-point batches of at least kDeferMinSegment points.
+constexpr int kDeferMinSegment = 2048;
+
+__device__ __forceinline__ void defer_plan(int m, int count, int target, int& segs, int& seg_len) {
+    int want = count > 0 ? (target + count - 1) / count : 1;
+    want = max(1, min(want, m / kDeferMinSegment));
+    seg_len = (int)(((int64_t)m + want - 1) / want);
+    seg_len = (seg_len + 15) & ~15;
+    segs = (int)(((int64_t)m + seg_len - 1) / seg_len);
+}
+
+// Item w: segment w / count of listed tile w % count (segment-major, so that
+// the waves resident together read the same data segment).  Sums go to
+// psum[(seg * 2 + {0, 1}) * count * 64 + position * 64 + lane].
+__global__ __launch_bounds__(kGroupSize) void aidw_f32_defer_part(ProblemF32 p, DeferWorkspace ws) {
+    const int count = *(const __attribute__((address_space(4))) int*)ws.count;
+    int segs, seg_len;
+    defer_plan(p.m, count, ws.target, segs, seg_len);
+    const int w = wave_id();
+    if (w >= count * segs) return;
+    const int seg = w / count;
+    const int pos = w - seg * count;
+    const int tile = __builtin_amdgcn_readfirstlane(ws.list[pos]);
+    const int j0 = seg * seg_len;
+    const int j1 = seg_end(p.m, j0, seg_len);
+    int qi[1];
+    float qx[1], qy[1];
+    load_queries<1>(p, tile * kWaveSize, qi, qx, qy);
+    const int c = qi[0] < p.n ? qi[0] : p.n - 1;
+    const float* qp = ws.qpar;
+    float na[1] = {qp[c]}, aL0[1] = {qp[p.n + c]};
+    double Sw[1] = {0.0}, Swz[1] = {0.0};
+    scan_wsum_any<1>(as_const(p.dx), as_const(p.dy), as_const(p.dz), j0, j1, qx, qy, na, aL0, Sw,
+                     Swz, (int)qp[3 * p.n + c], qp[2 * p.n + c], p.zmax);
+    const int64_t slot = (int64_t)pos * kWaveSize + lane_id();
+    const int64_t stride = (int64_t)count * kWaveSize;
+    ws.psum[(int64_t)seg * 2 * stride + slot] = Sw[0];
+    ws.psum[((int64_t)seg * 2 + 1) * stride + slot] = Swz[0];
+}
+
+// The segments of each listed query added in order, then the ratio.
+__global__ __launch_bounds__(kGroupSize) void aidw_f32_defer_reduce(ProblemF32 p,
+                                                                    DeferWorkspace ws) {
+    const int count = *(const __attribute__((address_space(4))) int*)ws.count;
+    const int t = blockIdx.x * kGroupSize + threadIdx.x;
+    const int pos = t / kWaveSize;
+    if (pos >= count) return;
+    const int q = ws.list[pos] * kWaveSize + (t - pos * kWaveSize);
+    if (q >= p.n) return;
+    int segs, seg_len;
+    defer_plan(p.m, count, ws.target, segs, seg_len);
+    const int64_t stride = (int64_t)count * kWaveSize;
+    double Sw = 0.0, Swz = 0.0;
+    for (int seg = 0; seg < segs; ++seg) {
+        Sw += ws.psum[(int64_t)seg * 2 * stride + t];
+        Swz += ws.psum[((int64_t)seg * 2 + 1) * stride + t];
+    }
+    p.out[q] = (float)(Swz / Sw);
+}
+
 // max |z| as the largest bit pattern of |z| (ordered like the values for
 // non-negative floats; NaN patterns sort above infinity).
 template <int T>
@@ -691,7 +945,8 @@ __device__ __forceinline__ void abs_max_block(const float* __restrict__ z, int m
 }
 
 __global__ __launch_bounds__(1024) void aidw_abs_max(const float* __restrict__ z, int m,
-                                                     float* __restrict__ out) {
+                                                     float* __restrict__ out, int* clear) {
+    if (clear && threadIdx.x == 0) *clear = 0;
     abs_max_block<1024>(z, m, out);
 }
 
@@ -722,7 +977,7 @@ template <int K>
 __device__ __forceinline__ void serve_item(const ServeJob& J, const ServeItem& it) {
     const ProblemF32& p = J.p;
     if (it.phase == kServeFused) {
-        fused_tile<K, 1, false>(p, it.tile * kWaveSize);
+        fused_tile<K, 1, false>(p, (alpha_ptr)&J.p.ap, it.tile * kWaveSize);
         return;
     }
     const int j0 = it.seg * J.sp.seg_len;
@@ -767,7 +1022,8 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_serve(const ServeJob* __r
     if (it >= n_items) return;
     const ServeItem w = items[it];
     if constexpr (TRACK)
-        fused_tile<K, 1, true>(jobs[w.job].p, w.tile * kWaveSize);  // jobs with knn_idx: unsplit
+        fused_tile<K, 1, true>(jobs[w.job].p, (alpha_ptr)&jobs[w.job].p.ap,
+                               w.tile * kWaveSize);  // jobs with knn_idx: unsplit
     else
         serve_item<K>(jobs[w.job], w);
 }
@@ -879,8 +1135,43 @@ hipError_t launch_aidw_f32(const ProblemF32& p, const LaunchF32& cfg, const Spli
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_abs_max(const float* z, int m, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(aidw_abs_max, dim3(1), dim3(1024), 0, s, z, m, out);
+hipError_t launch_abs_max(const float* z, int m, float* out, hipStream_t s, int* clear) {
+    hipLaunchKernelGGL(aidw_abs_max, dim3(1), dim3(1024), 0, s, z, m, out, clear);
+    return hipGetLastError();
+}
+
+size_t spec_workspace_bytes(int64_t n, int target, DeferWorkspace* ws, char* base) {
+    const int64_t tiles = (n + kWaveSize - 1) / kWaveSize;
+    const size_t a = 256;
+    auto up = [&](size_t v) { return (v + a - 1) / a * a; };
+    // count * segments < target + count <= target + tiles items
+    const size_t sizes[4] = {sizeof(int), sizeof(int) * (size_t)tiles, 4 * sizeof(float) * (size_t)n,
+                             2 * sizeof(double) * (size_t)kWaveSize * (size_t)(target + tiles)};
+    size_t off[4], bytes = 0;
+    for (int i = 0; i < 4; ++i) {
+        off[i] = bytes;
+        bytes += up(sizes[i]);
+    }
+    if (ws) {
+        ws->count = reinterpret_cast<int*>(base + off[0]);
+        ws->list = reinterpret_cast<int*>(base + off[1]);
+        ws->qpar = reinterpret_cast<float*>(base + off[2]);
+        ws->psum = reinterpret_cast<double*>(base + off[3]);
+        ws->target = target;
+    }
+    return bytes;
+}
+
+template <int K>
+hipError_t launch_spec_k(const ProblemF32& p, const DeferWorkspace& ws, hipStream_t stream) {
+    const int64_t tiles = (p.n + kWaveSize - 1) / kWaveSize;
+    hipLaunchKernelGGL((aidw_f32_fused_spec<K>), dim3(groups_for(tiles)), dim3(kGroupSize), 0,
+                       stream, p, ws);
+    hipLaunchKernelGGL(aidw_f32_defer_part, dim3(groups_for(ws.target + tiles)), dim3(kGroupSize),
+                       0, stream, p, ws);
+    hipLaunchKernelGGL(aidw_f32_defer_reduce,
+                       dim3((unsigned)((tiles * kWaveSize + kGroupSize - 1) / kGroupSize)),
+                       dim3(kGroupSize), 0, stream, p, ws);
     return hipGetLastError();
 }
 
@@ -899,6 +1190,16 @@ hipError_t launch_aidw_f32_pass2(const ProblemF32& p, SplitPlan sp, const float*
     hipLaunchKernelGGL(aidw_f32_wsum_reduce, dim3((unsigned)((p.n + kGroupSize - 1) / kGroupSize)),
                        dim3(kGroupSize), 0, stream, p, sp, psum);
     return hipGetLastError();
+}
+
+hipError_t launch_aidw_f32_spec(const ProblemF32& p, const DeferWorkspace& ws,
+                                hipStream_t stream) {
+    if (p.n <= 0) return hipSuccess;
+    if (p.spec_power < 1 || p.spec_power > 8) return hipErrorInvalidValue;
+#define CALL(KK) launch_spec_k<KK>(p, ws, stream)
+    AIDW_K_DISPATCH(k_bucket(p.ap.k), CALL)
+#undef CALL
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_aidw_f32_batch(const BatchLaunch& b, hipStream_t stream) {
