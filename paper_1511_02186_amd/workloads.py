@@ -186,6 +186,31 @@ def batched(count=512, seed=3, m_range=(1024, 65536), n_range=(1024, 32768),
     return out
 
 
+def dense_patch(m=16384, n=2048, seed=5, k=15, dtype=np.float32, patch_frac=0.3,
+                patch_queries=0.25):
+    """U[0,1]^2 data with a fraction `patch_frac` of the points moved into the
+    square [0.45, 0.55]^2 (forty times the background density there), and
+    queries: the first `patch_queries` of them inside that square, the rest
+    U[0,1]^2.  Queries in the patch have far nearer neighbours than m points
+    spread over the bounding box would give, so R falls below R_max there and
+    alpha below alpha_5; elsewhere alpha is alpha_5 for nearly every query.
+    z = sin(4x)cos(3y) + N(0, 0.01^2)."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.0, 1.0, m)
+    y = rng.uniform(0.0, 1.0, m)
+    z_noise = rng.normal(0.0, 0.01, m)
+    n_patch = int(round(patch_frac * m))
+    x[:n_patch] = rng.uniform(0.45, 0.55, n_patch)
+    y[:n_patch] = rng.uniform(0.45, 0.55, n_patch)
+    z = np.sin(4.0 * x) * np.cos(3.0 * y) + z_noise
+    qx = rng.uniform(0.0, 1.0, n)
+    qy = rng.uniform(0.0, 1.0, n)
+    nq = int(round(patch_queries * n))
+    qx[:nq] = rng.uniform(0.45, 0.55, nq)
+    qy[:nq] = rng.uniform(0.45, 0.55, nq)
+    return _finish("dense_patch_m%d_n%d" % (m, n), x, y, z, qx, qy, k, dtype, {"seed": seed})
+
+
 def uniform_unit(m, n, seed, k, dtype=np.float32):
     """m data and n query points U[0,1]^2, z = sin(4x)cos(3y) + N(0, 0.01^2)."""
     inst = uniform_small(m, n, seed, k, dtype)

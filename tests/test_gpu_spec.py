@@ -1,0 +1,158 @@
+"""The speculative single pass of the unsplit FP32-scaled kernel.
+
+When alpha_5 is a whole power, pass 1 also forms the unscaled pass-2 sums of
+that power; tiles whose 64 queries all end at alpha_5 are done after one scan,
+the others get pass 2 afterwards in data segments.  These tests force the
+unsplit launch (split_segments = 1) so that small problems take that path, and
+check it against the FP64 oracle and against the two-pass kernel (the
+deterministic handle runs that one), with tiles that keep the speculation,
+tiles that lose it, and problems where it is never tried.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1511_02186_amd import aidw, workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    c = aidw.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx_det(torch):
+    c = aidw.Context(0, deterministic=1)
+    yield c
+    c.close()
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def run(c, inst, split=1, levels=None):
+    """(out, r_obs, alpha) of an unsplit launch on handle c."""
+    data_xy, data_z, query_xy = aidw.to_device(inst)
+    c.set_tuning(0, 0, split)
+    try:
+        out, r_obs, alpha, _ = c.interpolate(data_xy, data_z, query_xy, inst.k,
+                                             levels or inst.levels, inst.R_min, inst.R_max,
+                                             inst.area, diag=True, knn=False)
+    finally:
+        c.set_tuning(0)
+    return out.cpu().numpy(), r_obs.cpu().numpy(), alpha.cpu().numpy()
+
+
+def oracle_check(inst, out, idx=None, levels=None):
+    idx = np.arange(inst.n) if idx is None else idx
+    lv = levels or inst.levels
+    args = (inst.data_x, inst.data_y)
+    want, _, a_ref, _ = oracle.run(*args, inst.data_z, inst.query_x[idx], inst.query_y[idx], inst.k,
+                                   lv, inst.R_min, inst.R_max, inst.area, diag=True)
+    scale = oracle.run(*args, np.abs(inst.data_z), inst.query_x[idx], inst.query_y[idx], inst.k,
+                       lv, inst.R_min, inst.R_max, inst.area)
+    err = float(np.max(np.abs(out[idx].astype(np.float64) - want) / scale))
+    return err, a_ref
+
+
+def failing_tiles(alpha, power=5.0):
+    pad = (-alpha.size) % 64
+    a = np.concatenate([alpha, np.full(pad, power)])
+    return int(np.sum((a.reshape(-1, 64) != power).any(axis=1)))
+
+
+def test_mixed_tiles_match_oracle_and_two_pass(ctx, ctx_det):
+    # a dense patch: 21 of 32 tiles leave the alpha_5 range, 11 keep it
+    inst = workloads.dense_patch()
+    say("speculative pass: dense patch m=%d n=%d k=%d" % (inst.m, inst.n, inst.k))
+    out, r_obs, alpha = run(ctx, inst)
+    err, a_ref = oracle_check(inst, out)
+    fails = failing_tiles(a_ref)
+    say("  tiles off alpha_5: %d of %d, max rel err vs oracle %.3e" % (fails, -(-inst.n // 64), err))
+    assert 0 < fails < -(-inst.n // 64)  # both kinds of tile are exercised
+    assert err <= TOL_F32
+    # pass 1 is the same multiset scan: r_obs and alpha are bit-identical
+    out2, r2, a2 = run(ctx_det, inst)
+    assert np.array_equal(r_obs, r2) and np.array_equal(alpha, a2)
+    # tiles that kept the speculation reproduce the two-pass sums bit for bit;
+    # deferred tiles add their data segments in another grouping
+    keep = np.repeat(~(alpha.reshape(-1, 64) != 5.0).any(axis=1), 64)[: inst.n]
+    assert np.array_equal(out[keep], out2[keep])
+    scale = np.max(np.abs(out2))
+    assert np.max(np.abs(out.astype(np.float64) - out2)) <= 1e-6 * scale
+
+
+def test_every_tile_deferred(ctx):
+    # clustered data with k = 8: few tiles keep alpha_5 everywhere
+    inst = workloads.clustered(m=8192, n=1000, seed=21, k=8)
+    out, _, alpha = run(ctx, inst)
+    err, a_ref = oracle_check(inst, out)
+    say("clustered k=8: tiles off alpha_5 %d of %d, err %.3e" % (failing_tiles(a_ref),
+                                                                  -(-inst.n // 64), err))
+    assert err <= TOL_F32
+
+
+def test_no_tile_deferred(ctx):
+    inst = workloads.uniform_unit(1 << 16, 1 << 12, seed=22, k=15)
+    out, _, alpha = run(ctx, inst)
+    idx = np.linspace(0, inst.n - 1, 128).astype(np.int64)
+    err, _ = oracle_check(inst, out, idx)
+    say("uniform k=15: queries off alpha_5 %d, err %.3e" % (int(np.sum(alpha != 5.0)), err))
+    assert err <= TOL_F32
+
+
+@pytest.mark.parametrize("levels", [(1, 2, 3, 4, 2.5), (0.5, 1, 1.5, 2, 2)])
+def test_other_powers(ctx, ctx_det, levels):
+    # alpha_5 = 2.5 is not whole: no speculation, the two-pass kernel runs;
+    # alpha_5 = 2 is: speculation with A = 2
+    inst = workloads.dense_patch(m=8192, n=1500, seed=23, k=10)
+    out, _, alpha = run(ctx, inst, levels=levels)
+    out2, _, _ = run(ctx_det, inst, levels=levels)
+    err, _ = oracle_check(inst, out, levels=levels)
+    assert err <= TOL_F32
+    if levels[4] != int(levels[4]):
+        assert np.array_equal(out, out2)
+
+
+def test_ragged_and_small(ctx):
+    # m just above the speculation threshold, n not a multiple of 64, and a
+    # data count that leaves a ragged batch tail
+    for m, n in ((1024, 65), (1037, 1), (3001, 777)):
+        inst = workloads.uniform_unit(m, n, seed=24 + m, k=15)
+        out, _, _ = run(ctx, inst)
+        err, _ = oracle_check(inst, out)
+        say("m=%d n=%d err %.3e" % (m, n, err))
+        assert err <= TOL_F32
+
+
+def test_noalloc_takes_the_same_path(ctx, torch):
+    inst = workloads.dense_patch(m=8192, n=1200, seed=25, k=15)
+    data_xy, data_z, query_xy = aidw.to_device(inst)
+    outs = []
+    for entry in (aidw.aidw_interpolate_ex, aidw.aidw_interpolate_noalloc):
+        out = torch.full((inst.n,), np.nan, dtype=torch.float32, device="cuda")
+        ctx.set_tuning(0, 0, 1)
+        try:
+            ctx.bind_current_stream()
+            p = ctx.problem(data_xy, data_z, query_xy, inst.k, out, inst.levels, inst.R_min,
+                            inst.R_max, inst.area)
+            assert entry(ctx.h, p) == aidw.AIDW_OK, aidw.last_error(ctx.h)
+        finally:
+            ctx.set_tuning(0)
+        torch.cuda.synchronize()
+        outs.append(out.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
