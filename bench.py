@@ -26,10 +26,13 @@ FLOP_PER_PAIR = 9.0          # pass 1: 6 FLOP, pass 2: 12 FLOP, mean 9
 PEAK_FP32_TFLOPS = 157.3     # 256 CU x 2.4 GHz x 128 lanes x 2 (FMA)
 
 
+# The sources that decide what one step launches and what those kernels do:
+# the traffic counters in the profile are used only while these are unchanged.
 KERNEL_SOURCES = ["paper_1511_02186_amd/csrc/kernels_f32.hip",
                   "paper_1511_02186_amd/csrc/device_math.h",
-                  "paper_1511_02186_amd/csrc/common.h"]
-TRAFFIC_PROFILE = "profiles/aidw_f32_fused_paper_scale_m1048576_n1048576.md"
+                  "paper_1511_02186_amd/csrc/common.h",
+                  "paper_1511_02186_amd/csrc/api.hip"]
+TRAFFIC_PROFILE = "profiles/aidw_f32_fused_spec_paper_scale_m1048576_n1048576.md"
 
 
 def kernel_sources_sha256():
@@ -85,24 +88,18 @@ def parse():
     ap.add_argument("--serve-sweep-requests", type=int, default=200,
                     help="requests of each lower-rate serving run (250, 500, 1000 req/s)")
     ap.add_argument("--ablation", action="store_true",
-                    help="also time the data-access designs (scalar / LDS-tiled / naive loads, "
-                         "SoA / AoaS) at the paper's sizes, end to end like its Table 1")
+                    help="time the data-access designs (scalar / LDS-tiled / naive loads, "
+                         "SoA / AoaS) at all of the paper's sizes, end to end like its Table 1 "
+                         "(the default run times the 1000K row only)")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the 1000K ablation row")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the plain FP64 small workload, the clustered workload and "
+                         "standard IDW")
     ap.add_argument("--check", type=int, default=64,
                     help="queries checked against the oracle after timing (0 = none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy, the reference for HBM counters")
     return ap.parse_args()
-
-
-def step_kernels(torch, inst):
-    """The kernels one step runs: the fused kernel while the 64-query tiles
-    give two rounds of 8 waves per SIMD, else the split-m launches (the
-    library's automatic plan)."""
-    cus = torch.cuda.get_device_properties(0).multi_processor_count
-    tiles = (inst.n + 63) // 64
-    if tiles >= 2 * cus * 4 * 8:
-        return "aidw_f32_fused"
-    return "aidw_f32_knn_part + aidw_f32_knn_merge + aidw_f32_wsum_part + aidw_f32_wsum_reduce"
 
 
 def main():
@@ -126,6 +123,10 @@ def main():
     def step():
         ctx.interpolate(data_xy, data_z, query_xy, inst.k, inst.levels, inst.R_min, inst.R_max,
                         inst.area, flags=aidw.AIDW_FLAG_ASYNC, out=out)
+
+    # what one step launches, as the library plans it
+    kernels = aidw.aidw_describe_launch(ctx.h, ctx.problem(
+        data_xy, data_z, query_xy, inst.k, out, inst.levels, inst.R_min, inst.R_max, inst.area))
 
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
@@ -176,7 +177,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": measured_traffic() if inst.m == inst.n == 1 << 20 else None,
-                     "kernel": step_kernels(torch, inst), "flop_per_pair_eval": FLOP_PER_PAIR},
+                     "kernel": kernels, "flop_per_pair_eval": FLOP_PER_PAIR,
+                     "duration": "all launches of one step (HIP events around the step)"},
         "step_ms": {"p10": float(np.percentile(per, 10)), "p50": float(np.median(per)),
                     "p90": float(np.percentile(per, 90)), "wall_s": wall},
     }
@@ -219,8 +221,16 @@ def main():
     if not args.no_grid:
         result["grid_knn"] = bench_grid(ctx, torch, aidw, step_args=(
             data_xy, data_z, query_xy, inst), full_ms=ms, pairs=pairs)
+    if not args.no_legs:
+        result["plain_fp64_small"] = bench_c1(ctx, torch, aidw, workloads)
+        result["clustered"] = bench_c3(ctx, torch, aidw, workloads)
+        result["standard_idw"] = bench_idw(ctx, torch, aidw, step_args=(
+            data_xy, data_z, query_xy, inst), aidw_ms=ms)
     if args.ablation:
         result["ablation"] = bench_ablation(ctx, torch, aidw, workloads)
+    elif not args.no_ablation:
+        result["ablation"] = bench_ablation(ctx, torch, aidw, workloads, sizes=(1024000,),
+                                            with_fp64=False)
     if not args.no_batch:
         result["batched"] = bench_batched(ctx, torch, aidw, workloads)
     if not args.no_serve:
@@ -252,7 +262,8 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def bench_ablation(ctx, torch, aidw, workloads, sizes=(10240, 51200, 102400, 512000, 1024000)):
+def bench_ablation(ctx, torch, aidw, workloads, sizes=(10240, 51200, 102400, 512000, 1024000),
+                   with_fp64=True):
     """The paper's Table 1 axes on this GPU: m = n = N points in a square,
     every data-access design and layout, the production launch and the plain
     FP64 kernel (FP32 against FP64, as the paper's Table 1 does).  Times
@@ -261,7 +272,7 @@ def bench_ablation(ctx, torch, aidw, workloads, sizes=(10240, 51200, 102400, 512
     designs = [("production", None, None)] + [
         ("%s_%s" % (a, l), ai, li)
         for ai, a in enumerate(["scalar", "tiled", "naive"])
-        for li, l in enumerate(["soa", "aoas"])] + [("plain_fp64", None, None)]
+        for li, l in enumerate(["soa", "aoas"])] + ([("plain_fp64", None, None)] if with_fp64 else [])
     rows = []
     for N in sizes:
         inst = workloads.paper_scale(m=N, n=N, seed=7)
@@ -302,6 +313,101 @@ def bench_ablation(ctx, torch, aidw, workloads, sizes=(10240, 51200, 102400, 512
                          "pair_evals_per_s": 2.0 * N * N / (kern * 1e-3)})
     return {"workload": "m = n = N uniform points in [0, 1000]^2, k = 15 (N as in the paper's "
                         "Table 1, 1K = 1024)", "rows": rows}
+
+
+def _time_ms(torch, run, reps):
+    """Median and minimum of `reps` HIP-event timings of run() on the current stream."""
+    run()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return float(np.median(times)), float(np.min(times))
+
+
+def bench_c1(ctx, torch, aidw, workloads, reps=20):
+    """The plain FP64 workload: m = n = 1024 uniform in [0,1]^2, k = 10, FP64
+    inputs and the plain FP64 kernel, checked against the oracle on every
+    query (relative error, and the fraction of queries whose k-nearest index
+    set equals the oracle's)."""
+    import oracle
+
+    print("bench: plain FP64, m = n = 1024", file=sys.stderr, flush=True)
+    inst = workloads.uniform_small(m=1024, n=1024, seed=0, dtype=np.float64)
+    d = aidw.to_device(inst)
+    out = torch.empty(inst.n, dtype=torch.float64, device="cuda")
+    knn = torch.empty((inst.n, inst.k), dtype=torch.int32, device="cuda")
+    ctx.bind_current_stream()
+    p = ctx.problem(*d, inst.k, out, inst.levels, inst.R_min, inst.R_max, inst.area, knn_idx=knn,
+                    flags=aidw.AIDW_FLAG_ASYNC)
+    kernels = aidw.aidw_describe_launch(ctx.h, p)
+    ms, ms_min = _time_ms(torch, lambda: aidw.check(aidw.aidw_interpolate_ex(ctx.h, p)), reps)
+    got, got_knn = out.cpu().numpy(), knn.cpu().numpy()
+    want, _, _, want_knn = oracle.run(inst.data_x, inst.data_y, inst.data_z, inst.query_x,
+                                      inst.query_y, inst.k, inst.levels, inst.R_min, inst.R_max,
+                                      inst.area, diag=True)
+    return {"workload": "m = n = 1024 U[0,1]^2, z = sin 4x cos 3y + N(0, 0.01^2), k = 10, FP64, "
+                        "seed 0", "kernel": kernels, "ms": ms, "ms_min": ms_min,
+            "pair_evals_per_s": inst.pair_evals() / (ms * 1e-3),
+            "max_rel_err_vs_oracle": float(np.max(np.abs(got - want) / np.abs(want))),
+            "knn_exact_frac": float(np.mean(np.all(np.sort(got_knn, 1) == np.sort(want_knn, 1), 1))),
+            "checked_queries": inst.n}
+
+
+def bench_c3(ctx, torch, aidw, workloads, reps=10, check=512):
+    """The clustered precision workload: m = n = 2^18, 64 Gaussian clusters
+    plus background, 1 % of the queries on data points, k = 10, FP32-scaled;
+    error against the oracle on sampled queries and on every on-point one."""
+    import oracle
+
+    print("bench: clustered, m = n = 2^18", file=sys.stderr, flush=True)
+    inst = workloads.clustered()
+    d = aidw.to_device(inst)
+    out = torch.empty(inst.n, dtype=torch.float32, device="cuda")
+    ctx.bind_current_stream()
+    p = ctx.problem(*d, inst.k, out, inst.levels, inst.R_min, inst.R_max, inst.area,
+                    flags=aidw.AIDW_FLAG_ASYNC)
+    kernels = aidw.aidw_describe_launch(ctx.h, p)
+    ms, ms_min = _time_ms(torch, lambda: aidw.check(aidw.aidw_interpolate_ex(ctx.h, p)), reps)
+    got = out.cpu().numpy()
+    on = np.asarray(inst.meta.get("on_point_queries", []), dtype=np.int64)
+    rng = np.random.default_rng(0)
+    idx = np.unique(np.concatenate([rng.choice(inst.n, check, replace=False), on[:256]]))
+    args = (inst.data_x, inst.data_y)
+    want = oracle.run(*args, inst.data_z, inst.query_x[idx], inst.query_y[idx], inst.k,
+                      inst.levels, inst.R_min, inst.R_max, inst.area)
+    scale = oracle.run(*args, np.abs(inst.data_z), inst.query_x[idx], inst.query_y[idx], inst.k,
+                       inst.levels, inst.R_min, inst.R_max, inst.area)
+    pairs = float(inst.pair_evals())
+    return {"workload": "m = n = 2^18, 90 % from 64 Gaussians (sigma 1e-4..1e-1) + 10 % "
+                        "uniform, 1 % of queries on data points, k = 10, FP32-scaled, seed 2",
+            "kernel": kernels, "ms": ms, "ms_min": ms_min, "pair_evals_per_s": pairs / (ms * 1e-3),
+            "frac_fp32_peak": FLOP_PER_PAIR * pairs / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+            "max_rel_err_vs_oracle": float(np.max(np.abs(got[idx] - want) / scale)),
+            "checked_queries": int(idx.size)}
+
+
+def bench_idw(ctx, torch, aidw, step_args, aidw_ms, reps=5):
+    """Standard IDW (Eq. 1, constant power) on the benchmark workload, beside
+    AIDW: the paper's comparison of the two (AIDW adds the kNN pass)."""
+    data_xy, data_z, query_xy, inst = step_args
+    out = torch.empty(inst.n, dtype=torch.float32, device=data_xy.device)
+    res = {}
+    for power in (2.0, 5.0):
+        print("bench: standard IDW, power %g" % power, file=sys.stderr, flush=True)
+        ctx.bind_current_stream()
+        p = ctx.problem(data_xy, data_z, query_xy, 1, out, area=1.0, flags=aidw.AIDW_FLAG_ASYNC)
+        q = ctx.problem(data_xy, data_z, query_xy, 1, out, (power,) * 5, 0.0, 1.0, 1.0)
+        kernels = aidw.aidw_describe_launch(ctx.h, q)
+        ms, ms_min = _time_ms(torch, lambda: aidw.check(aidw.aidw_idw(ctx.h, p, power)), reps)
+        res["power_%g" % power] = {"kernel": kernels, "ms": ms, "ms_min": ms_min,
+                                   "aidw_over_idw_time": aidw_ms / ms}
+    return res
 
 
 def bench_grid(ctx, torch, aidw, step_args, full_ms, pairs, steps=3):

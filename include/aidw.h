@@ -168,6 +168,15 @@ aidw_status aidw_interpolate(aidw_t h, const void* data_xy, const void* data_z, 
  * hipGraph; aidw_batch_* captures and replays launches. */
 aidw_status aidw_interpolate_ex(aidw_t h, const aidw_problem* p);
 
+/* The kernels that aidw_interpolate_ex would launch for *p on this handle
+ * (its tuning and options included), as text: kernel names as a profiler
+ * shows them, joined by " + " in launch order, with the template arguments
+ * of the k bucket (and queries per lane) chosen; empty for n == 0.  Writes at
+ * most cap bytes including the terminating NUL (longer text is cut).
+ * Launches nothing.  AIDW_EINVAL for an invalid problem or a NULL or empty
+ * buffer. */
+aidw_status aidw_describe_launch(aidw_t h, const aidw_problem* p, char* buf, size_t cap);
+
 /* For callers that cannot allocate device memory: code being captured into
  * a hipGraph, tight serving loops, harnesses that forbid hipMalloc.  Same
  * problem, results and errors as aidw_interpolate_ex, but the call

@@ -131,6 +131,8 @@ _SIGNATURES = {
                                         ctypes.c_void_p]),
     "aidw_interpolate_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem)]),
     "aidw_interpolate_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem)]),
+    "aidw_describe_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem),
+                                            ctypes.c_char_p, ctypes.c_size_t]),
     "aidw_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_tuning)]),
     "aidw_idw": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem), ctypes.c_double]),
     "aidw_interpolate_variant": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem),
@@ -242,6 +244,13 @@ def aidw_interpolate_ex(h, problem: aidw_problem) -> int:
 
 def aidw_interpolate_noalloc(h, problem: aidw_problem) -> int:
     return lib().aidw_interpolate_noalloc(h, ctypes.byref(problem))
+
+
+def aidw_describe_launch(h, problem: aidw_problem) -> str:
+    """The kernels aidw_interpolate_ex would launch for `problem` (raises on error)."""
+    buf = ctypes.create_string_buffer(1024)
+    check(lib().aidw_describe_launch(h, ctypes.byref(problem), buf, len(buf)))
+    return buf.value.decode()
 
 
 def aidw_idw(h, problem: aidw_problem, power: float) -> int:

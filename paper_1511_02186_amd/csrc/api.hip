@@ -275,6 +275,11 @@ aidw::ProblemF32 problem_f32(const aidw_problem* p) {
         q.spec_power = (int)a5;
         const double R90 = std::min(p->R_max, p->R_min + std::acos(-0.8) * p->R_max / M_PI);
         q.spec_dist_sum = (float)(p->k * R90 * q.ap.r_exp * (1.0 - 1e-4));
+        // with all five levels equal alpha never leaves alpha_5 (standard IDW):
+        // never stop speculating early
+        bool constant = true;
+        for (int j = 0; j < 4; ++j) constant &= p->alpha_levels[j] == a5;
+        if (constant) q.spec_dist_sum = 0.0f;
     }
     return q;
 }
@@ -584,6 +589,42 @@ aidw_status aidw_interpolate_ex(aidw_t h, const aidw_problem* p) {
     ErrorScope es(h);
     if (!h) return fail(AIDW_EINVAL, "handle is NULL");
     return run_problem(h, p);
+}
+
+aidw_status aidw_describe_launch(aidw_t h, const aidw_problem* p, char* buf, size_t cap) {
+    ErrorScope es(h);
+    if (!h) return fail(AIDW_EINVAL, "handle is NULL");
+    if (!buf || cap == 0) return fail(AIDW_EINVAL, "buffer is NULL or empty");
+    aidw_status st = validate(p);
+    if (st != AIDW_OK) return st;
+    std::string d;
+    const int K = aidw::k_bucket(p->k);
+    const std::string k = "<" + std::to_string(K);
+    if (p->n == 0) {
+        d = "";
+    } else if (p->flags & AIDW_FLAG_GRID_KNN) {
+        d = "aidw_abs_max + bbox_partial + grid_setup + grid_clear + grid_count + "
+            "(device scan) + grid_scatter + grid_knn" + k + "> + aidw_f32_wsum_part + "
+            "aidw_f32_wsum_reduce";
+    } else if (p->precision == AIDW_FP64) {
+        d = "aidw_f64_plain" + k + (p->knn_idx ? ", true>" : ", false>");
+    } else {
+        const F32Plan pl = plan_f32(h, p);
+        if (pl.spec)
+            d = "aidw_abs_max + aidw_f32_fused_spec" + k + "> + aidw_f32_defer_part + "
+                "aidw_f32_defer_reduce";
+        else if (pl.sp.segments > 1)
+            d = "aidw_abs_max + aidw_f32_knn_part" + k + "> + aidw_f32_knn_merge" + k +
+                "> + aidw_f32_wsum_part + aidw_f32_wsum_reduce (" +
+                std::to_string(pl.sp.segments) + " data segments)";
+        else
+            d = "aidw_abs_max + aidw_f32_fused" + k + ", " + std::to_string(pl.cfg.q_per_lane) +
+                (p->knn_idx ? ", true>" : ", false>");
+    }
+    const size_t len = std::min(d.size(), cap - 1);
+    memcpy(buf, d.data(), len);
+    buf[len] = '\0';
+    return AIDW_OK;
 }
 
 aidw_status aidw_interpolate_noalloc(aidw_t h, const aidw_problem* p) {
