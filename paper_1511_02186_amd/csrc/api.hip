@@ -371,9 +371,18 @@ F32Plan plan_f32(const aidw_ctx* h, const aidw_problem* p) {
     if (!p->knn_idx) pl.sp = split_plan_for(h, t, p->m, p->n);
     // The speculative single pass replaces the unsplit one-query-per-lane
     // kernel when alpha_5 is a whole power; it is off in deterministic mode,
-    // which promises the kernel batched launches use.
-    pl.spec = !h->deterministic && !p->knn_idx && pl.sp.segments == 1 && pl.cfg.q_per_lane == 1 &&
-              pl.cfg.max_waves_per_simd == 0 && problem_f32(p).spec_power != 0;
+    // which promises the kernel batched launches use.  It fills the device
+    // better than the two-pass kernel (8 waves per SIMD, one scan), so the
+    // automatic plan keeps it unsplit down to half a round of query tiles
+    // (m = 2^20: n = 2^18 81.0 against 81.9 ms split, n = 2^19 138 against
+    // 158 ms; at a quarter round, n = 2^17, the split is ahead, 42 against
+    // 46 ms).
+    const bool spec_ok = !h->deterministic && !p->knn_idx && pl.cfg.q_per_lane == 1 &&
+                         pl.cfg.max_waves_per_simd == 0 && problem_f32(p).spec_power != 0;
+    if (spec_ok && t.split_segments == 0 && pl.sp.segments > 1 &&
+        2 * (int64_t)pl.sp.tiles >= round_waves(h))
+        pl.sp = aidw::SplitPlan{1, (int)p->m, pl.sp.tiles};
+    pl.spec = spec_ok && pl.sp.segments == 1;
     return pl;
 }
 

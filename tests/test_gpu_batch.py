@@ -217,16 +217,41 @@ def test_automatic_split_for_few_queries(ctx, torch, m, n):
     assert rel_err(out[idx], o, scale).max() <= TOL_F32
 
 
-def test_automatic_split_boundary_two_rounds(ctx, torch):
-    """The automatic plan keeps the fused kernel from two rounds of 64-query
-    tiles (8 waves per SIMD) up and splits m one tile below.  The same
-    queries, run both ways: identical k-nearest statistics, outputs equal to
-    FP64 summation order, and both within the bar on sampled queries."""
+def _plan(ctx, torch, inst, n, levels):
+    data_xy, data_z, query_xy = aidw.to_device(inst)
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    p = ctx.problem(data_xy, data_z, query_xy[:, :n].contiguous(), inst.k, out, levels,
+                    inst.R_min, inst.R_max, inst.area)
+    return aidw.aidw_describe_launch(ctx.h, p)
+
+
+def test_automatic_split_boundaries(ctx, torch):
+    """The automatic plan splits m below two rounds of 64-query tiles (8
+    waves per SIMD) for the two-pass kernel, and below half a round when the
+    speculative single pass applies (alpha_5 whole)."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    rnd = cus * 4 * 8 * 64  # queries in one round of tiles
+    inst = workloads.paper_scale(m=1 << 14, n=2 * rnd, seed=78, k=15)
+    whole5, frac5 = (1, 2, 3, 4, 5), (1, 2, 3, 4, 4.5)
+    assert "aidw_f32_fused_spec<16>" in _plan(ctx, torch, inst, 2 * rnd, whole5)
+    assert "aidw_f32_fused_spec<16>" in _plan(ctx, torch, inst, rnd // 2, whole5)
+    assert "aidw_f32_knn_part<16>" in _plan(ctx, torch, inst, rnd // 2 - 64, whole5)
+    assert "aidw_f32_fused<16, 1, false>" in _plan(ctx, torch, inst, 2 * rnd, frac5)
+    assert "aidw_f32_knn_part<16>" in _plan(ctx, torch, inst, 2 * rnd - 64, frac5)
+
+
+@pytest.mark.parametrize("levels", [(1, 2, 3, 4, 5), (1, 2, 3, 4, 4.5)])
+def test_automatic_split_boundary(ctx, torch, levels):
+    """The same queries run on both sides of the automatic split boundary:
+    identical k-nearest statistics, outputs equal to FP64 summation order, and
+    both within the bar on sampled queries."""
     import copy
 
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    n = 2 * cus * 4 * 8 * 64
+    rnd = cus * 4 * 8 * 64
+    n = rnd // 2 if levels[4] == int(levels[4]) else 2 * rnd
     inst = workloads.paper_scale(m=1 << 16, n=n, seed=77, k=15)
+    inst.levels = levels
     below = copy.copy(inst)
     below.query_x = np.ascontiguousarray(inst.query_x[: n - 64])
     below.query_y = np.ascontiguousarray(inst.query_y[: n - 64])
