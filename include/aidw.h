@@ -238,6 +238,12 @@ typedef struct aidw_tuning {
                                 processed in parallel (1: never split); chosen
                                 automatically when the 64-query tiles give fewer
                                 than two rounds of 8 waves per SIMD */
+    int speculate;           /* 0: when alpha_5 is a whole power in [1, 8], pass 1
+                                also forms the pass-2 sums of that power, which
+                                stand for every 64-query tile whose queries all end
+                                at alpha_5 (pass 2 then runs only for the other
+                                tiles; results equal to the two-pass sums, bit for
+                                bit for the tiles that kept them); 1: never */
 } aidw_tuning;
 
 /* Fix the launch shape used for FP32-scaled problems (NULL restores the

@@ -75,7 +75,7 @@ class aidw_problem(ctypes.Structure):
 
 class aidw_tuning(ctypes.Structure):
     _fields_ = [("q_per_lane", ctypes.c_int), ("max_waves_per_simd", ctypes.c_int),
-                ("split_segments", ctypes.c_int)]
+                ("split_segments", ctypes.c_int), ("speculate", ctypes.c_int)]
 
 
 class aidw_server_options(ctypes.Structure):
@@ -277,10 +277,10 @@ def aidw_tune_load(h, path) -> int:
 
 
 def aidw_set_tuning(h, q_per_lane: int = 0, max_waves_per_simd: int = 0,
-                    split_segments: int = 0) -> int:
-    if not q_per_lane and not max_waves_per_simd and not split_segments:
+                    split_segments: int = 0, speculate: int = 0) -> int:
+    if not q_per_lane and not max_waves_per_simd and not split_segments and not speculate:
         return lib().aidw_set_tuning(h, None)
-    t = aidw_tuning(int(q_per_lane), int(max_waves_per_simd), int(split_segments))
+    t = aidw_tuning(int(q_per_lane), int(max_waves_per_simd), int(split_segments), int(speculate))
     return lib().aidw_set_tuning(h, ctypes.byref(t))
 
 
@@ -440,8 +440,8 @@ class Context:
             pass
 
     def set_tuning(self, q_per_lane: int = 0, max_waves_per_simd: int = 0,
-                   split_segments: int = 0):
-        check(aidw_set_tuning(self.h, q_per_lane, max_waves_per_simd, split_segments))
+                   split_segments: int = 0, speculate: int = 0):
+        check(aidw_set_tuning(self.h, q_per_lane, max_waves_per_simd, split_segments, speculate))
 
     def bind_current_stream(self):
         import torch

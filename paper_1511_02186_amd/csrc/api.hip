@@ -241,18 +241,25 @@ aidw::SplitPlan grid_pass2_plan(const aidw_ctx* h, const aidw_tuning& t, int64_t
 
 size_t split_workspace_bytes(const aidw::SplitPlan& sp, int k, int64_t n, aidw::SplitWorkspace* ws,
                              char* base) {
+    const int64_t tiles = (n + aidw::kWaveSize - 1) / aidw::kWaveSize;
     const size_t part = (size_t)sp.segments * k * n * sizeof(float);
     const size_t qpar = 4 * (size_t)n * sizeof(float);
     const size_t psum = (size_t)sp.segments * 2 * n * sizeof(double);
+    const size_t seg_ok = (size_t)sp.segments * tiles * sizeof(int);
     const size_t a = 256;
-    const size_t o_qpar = (part + a - 1) / a * a;
-    const size_t o_psum = (o_qpar + qpar + a - 1) / a * a;
+    auto up = [&](size_t v) { return (v + a - 1) / a * a; };
+    const size_t o_qpar = up(part);
+    const size_t o_psum = up(o_qpar + qpar);
+    const size_t o_seg = up(o_psum + psum);
+    const size_t o_tile = up(o_seg + seg_ok);
     if (ws) {
         ws->part = reinterpret_cast<float*>(base);
         ws->qpar = reinterpret_cast<float*>(base + o_qpar);
         ws->psum = reinterpret_cast<double*>(base + o_psum);
+        ws->seg_ok = reinterpret_cast<int*>(base + o_seg);
+        ws->tile_ok = reinterpret_cast<int*>(base + o_tile);
     }
-    return o_psum + psum;
+    return o_tile + tiles * sizeof(int);
 }
 
 // Problems of fewer data points than this keep the two passes: the single
@@ -353,6 +360,10 @@ struct F32Plan {
     bool spec;  // the speculative single pass, with pass 2 deferred for failed tiles
 };
 
+// Speculative sums (the single pass, or per segment in the split kernels)
+// unless the handle is deterministic or its tuning turns them off.
+bool speculation_allowed(const aidw_ctx* h) { return !h->deterministic && h->tuning.speculate != 1; }
+
 // Waves in one round of the device (8 per SIMD, 4 SIMDs per CU): what the
 // deferred pass 2 of the speculative launch aims to fill.
 int round_waves(const aidw_ctx* h) { return (h->cu_count > 0 ? h->cu_count : 256) * 4 * 8; }
@@ -370,19 +381,12 @@ F32Plan plan_f32(const aidw_ctx* h, const aidw_problem* p) {
                aidw::SplitPlan{1, (int)p->m, 0}, false};
     if (!p->knn_idx) pl.sp = split_plan_for(h, t, p->m, p->n);
     // The speculative single pass replaces the unsplit one-query-per-lane
-    // kernel when alpha_5 is a whole power; it is off in deterministic mode,
-    // which promises the kernel batched launches use.  It fills the device
-    // better than the two-pass kernel (8 waves per SIMD, one scan), so the
-    // automatic plan keeps it unsplit down to half a round of query tiles
-    // (m = 2^20: n = 2^18 81.0 against 81.9 ms split, n = 2^19 138 against
-    // 158 ms; at a quarter round, n = 2^17, the split is ahead, 42 against
-    // 46 ms).
-    const bool spec_ok = !h->deterministic && !p->knn_idx && pl.cfg.q_per_lane == 1 &&
-                         pl.cfg.max_waves_per_simd == 0 && problem_f32(p).spec_power != 0;
-    if (spec_ok && t.split_segments == 0 && pl.sp.segments > 1 &&
-        2 * (int64_t)pl.sp.tiles >= round_waves(h))
-        pl.sp = aidw::SplitPlan{1, (int)p->m, pl.sp.tiles};
-    pl.spec = spec_ok && pl.sp.segments == 1;
+    // kernel when alpha_5 is a whole power (a split problem speculates per
+    // segment, inside the split kernels); it is off in deterministic mode,
+    // which promises the kernel batched launches use.
+    pl.spec = !h->deterministic && !p->knn_idx && pl.cfg.q_per_lane == 1 &&
+              pl.cfg.max_waves_per_simd == 0 && pl.sp.segments == 1 &&
+              speculation_allowed(h) && problem_f32(p).spec_power != 0;
     return pl;
 }
 
@@ -407,6 +411,7 @@ hipError_t launch_f32(aidw_t h, const aidw_problem* p, const F32Plan& pl, char* 
         if (e == hipSuccess) e = aidw::launch_aidw_f32_spec(q, dw, h->stream);
         return e;
     }
+    if (!speculation_allowed(h)) q.spec_power = 0;  // the split kernels speculate when it is set
     aidw::SplitWorkspace ws{};
     if (pl.sp.segments > 1) split_workspace_bytes(pl.sp, p->k, p->n, &ws, w + kZmaxSlot);
     float* zmax = reinterpret_cast<float*>(w);
@@ -722,6 +727,7 @@ aidw_status aidw_set_tuning(aidw_t h, const aidw_tuning* t) {
         return fail(AIDW_EINVAL, "q_per_lane must be 0, 1, 2 or 4");
     if (t->max_waves_per_simd < 0 || t->max_waves_per_simd > 8)
         return fail(AIDW_EINVAL, "max_waves_per_simd must be in [0, 8]");
+    if (t->speculate != 0 && t->speculate != 1) return fail(AIDW_EINVAL, "speculate must be 0 or 1");
     h->tuning = *t;
     return AIDW_OK;
 }

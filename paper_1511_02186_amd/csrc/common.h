@@ -91,6 +91,9 @@ struct SplitWorkspace {
     float* qpar;   // [4][n] per query: -alpha/2, (alpha/2) log2 d_min^2, d_min,
                    // and the whole power of the one-transcendental pass 2 (0: none)
     double* psum;  // [segments][2][n] per-segment sum w and sum w z
+    // speculative sums (when the problem's spec_power is set):
+    int* seg_ok;   // [segments][tiles] 1 where pass 1 formed the segment's sums
+    int* tile_ok;  // [tiles] 1 where those sums stand for every segment
 };
 
 // Workspace of the speculative single-pass launch (spec_workspace_bytes):

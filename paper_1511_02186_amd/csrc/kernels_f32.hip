@@ -504,31 +504,71 @@ __device__ __forceinline__ void scan_knn_wsum_int(cptr X, cptr Y, cptr Z, int j0
     }
 }
 
-// Pass 1 with speculative sums for power A over a prefix of the points.
-// After the first eighth of the points the wave checks that in every lane
-// the k neighbour distances found so far still sum to at least
-// p.spec_dist_sum, i.e. that R is still in the range where Eq. 6 gives
-// alpha_5 (R only falls as points are added, so a lane below it seldom comes
-// back); if so the speculation goes on to the end, else it stops there.
-// Returns the first point that pass 1 has not seen: m when the sums in Sw,
-// Swz cover every point, else where the plain scan must continue.
+// Pass 1 over [j0, j1) with speculative sums for power A.  Early in the
+// range (see kSpecCheckAt) the wave predicts each lane's final R: in a random
+// order of the data the k-th distances shrink with the square root of the
+// points seen, so the sum of the k distances found so far, times
+// sqrt(seen / m), estimates the final sum.  If in some lane that estimate is
+// below kSpecKeep times p.spec_dist_sum (the sum at which Eq. 5 reaches
+// mu_R = 0.9, below which Eq. 6 leaves alpha_5), the speculation stops there
+// and the scan goes on as plain pass 1.  The bias towards going on reflects
+// the costs: a tile that gives up in vain needs a second scan later, one that
+// goes on in vain has formed sums for nothing.
+// Returns the first point that pass 1 has not seen: j1 when the sums in Sw,
+// Swz cover the whole range, else where the plain scan must continue.
+constexpr float kSpecKeep = 0.75f;
+// The check comes after 1/kSpecCheckAt of the range, but after at least
+// kSpecCheckMin points (a sample the k-th distance can be read from).
+constexpr int kSpecCheckAt = 32;
+constexpr int kSpecCheckMin = 512;
+
 template <int K, int A>
-__device__ __forceinline__ int knn_speculative(const ProblemF32& p, float qx, float qy,
-                                               float (&top)[K], double& Sw, double& Swz) {
+__device__ __forceinline__ int knn_speculative(const ProblemF32& p, int j0, int j1, float qx,
+                                               float qy, float (&top)[K], double& Sw, double& Swz) {
     cptr X = as_const(p.dx), Y = as_const(p.dy), Z = as_const(p.dz);
-    const int jc = (p.m / 8) & ~(batch2_for<1>() - 1);
-    int j0 = 0, j1 = jc;
-    for (;;) {
-        scan_knn_wsum_int<K, A>(X, Y, Z, j0, j1, qx, qy, top, Sw, Swz);
-        if (j1 == p.m) return p.m;
+    const int jc = j0 + ((max((j1 - j0) / kSpecCheckAt, min(j1 - j0, kSpecCheckMin))) &
+                         ~(batch2_for<1>() - 1));
+    scan_knn_wsum_int<K, A>(X, Y, Z, j0, jc, qx, qy, top, Sw, Swz);
+    if (jc > j0) {
         float s = 0.0f;  // -inf padding entries add nothing
 #pragma unroll
         for (int i = 0; i < K; ++i)
             if (top[i] > -INFINITY) s += __builtin_sqrtf(top[i]);
-        if (!__all(s >= p.spec_dist_sum)) return j1;
-        j0 = j1;
-        j1 = p.m;
+        const float predicted = s * __builtin_sqrtf((float)(jc - j0) / (float)p.m);
+        if (!__all(predicted >= kSpecKeep * p.spec_dist_sum)) return jc;
     }
+    scan_knn_wsum_int<K, A>(X, Y, Z, jc, j1, qx, qy, top, Sw, Swz);
+    return j1;
+}
+
+// Pass 1 of one lane's query over [j0, j1), with the speculative sums of
+// p.spec_power when that is set.  Returns true when Sw, Swz hold those sums
+// for the whole range.
+template <int K>
+__device__ __forceinline__ bool knn_maybe_speculative(const ProblemF32& p, int j0, int j1, float qx,
+                                                      float qy, float (&top)[K], double& Sw,
+                                                      double& Swz) {
+    int jscan = j0;
+    switch (p.spec_power) {
+#define AIDW_SPEC_CASE(A)                                                   \
+    case A:                                                                 \
+        jscan = knn_speculative<K, A>(p, j0, j1, qx, qy, top, Sw, Swz);      \
+        break;
+        AIDW_SPEC_CASE(1) AIDW_SPEC_CASE(2) AIDW_SPEC_CASE(3) AIDW_SPEC_CASE(4)
+        AIDW_SPEC_CASE(5) AIDW_SPEC_CASE(6) AIDW_SPEC_CASE(7) AIDW_SPEC_CASE(8)
+#undef AIDW_SPEC_CASE
+        default:
+            break;
+    }
+    float qxa[1] = {qx}, qya[1] = {qy};
+    float topa[1][K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) topa[0][i] = top[i];
+    int tix[1][1];
+    scan_knn<K, 1, false>(as_const(p.dx), as_const(p.dy), jscan, j1, qxa, qya, topa, tix);
+#pragma unroll
+    for (int i = 0; i < K; ++i) top[i] = topa[0][i];
+    return p.spec_power != 0 && jscan == j1;
 }
 
 template <int A>
@@ -685,21 +725,8 @@ __device__ __forceinline__ void spec_tile(const ProblemF32& p, alpha_ptr app, in
     int tix[1][1];
     init_lists<K, 1, false>(top, tix, p.ap.k);
     double Sw = 0.0, Swz = 0.0;
-    int spec = 0;   // the power whose sums cover every point, or 0
-    int jscan = 0;  // where the plain pass 1 continues
-    switch (p.spec_power) {
-#define AIDW_SPEC_CASE(A)                                                    \
-    case A:                                                                  \
-        jscan = knn_speculative<K, A>(p, qx[0], qy[0], top[0], Sw, Swz);      \
-        spec = jscan == p.m ? A : 0;                                         \
-        break;
-        AIDW_SPEC_CASE(1) AIDW_SPEC_CASE(2) AIDW_SPEC_CASE(3) AIDW_SPEC_CASE(4)
-        AIDW_SPEC_CASE(5) AIDW_SPEC_CASE(6) AIDW_SPEC_CASE(7) AIDW_SPEC_CASE(8)
-#undef AIDW_SPEC_CASE
-        default:
-            break;
-    }
-    scan_knn<K, 1, false>(as_const(p.dx), as_const(p.dy), jscan, p.m, qx, qy, top, tix);
+    const bool covered = knn_maybe_speculative<K>(p, 0, p.m, qx[0], qy[0], top[0], Sw, Swz);
+    const int spec = covered ? p.spec_power : 0;  // the power whose sums cover every point
 
     float na[1], aL0[1], d2min[1];
     int ipw;
@@ -756,9 +783,11 @@ __device__ __forceinline__ void store_partial(const float (&top)[K], const Probl
                                               int q, float* __restrict__ part) {
     if (q >= p.n) return;
     const int k = p.ap.k, pad = K - k;
+    // padding entries are -inf, real ones >= 0: a test of the value, not of
+    // i >= pad, whose uniform masks would stay in SGPRs through the scan
 #pragma unroll
     for (int i = 0; i < K; ++i)
-        if (i >= pad) part[((int64_t)seg * k + (i - pad)) * p.n + q] = top[i];
+        if (top[i] > -INFINITY) part[((int64_t)seg * k + (i - pad)) * p.n + q] = top[i];
 }
 
 // Fold the segment lists of query q in segment order (so equal distances
@@ -797,9 +826,15 @@ __device__ __forceinline__ int seg_end(int m, int j0, int seg_len) {
 
 // Waves are numbered segment-major so that the waves of one workgroup share a
 // data segment.
+// With p.spec_power set, an item also forms its segment's unscaled sums of
+// that power (as the speculative single pass does for the whole range) and
+// writes them where the segment's pass-2 item would, marking
+// ws.seg_ok[seg][tile]; the merge then decides per tile whether pass 2 is
+// needed at all.  The sums are those of the pass-2 item bit for bit (same
+// batches from the segment start, same order and rounding).
 template <int K>
 __global__ __launch_bounds__(kGroupSize) void aidw_f32_knn_part(ProblemF32 p, SplitPlan sp,
-                                                                float* __restrict__ part) {
+                                                                SplitWorkspace ws) {
     const int wave = wave_id();
     const int seg = wave / sp.tiles;
     const int tile = wave - seg * sp.tiles;
@@ -812,28 +847,50 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_knn_part(ProblemF32 p, Sp
     float top[1][K];
     int tix[1][1];
     init_lists<K, 1, false>(top, tix, p.ap.k);
-    scan_knn<K, 1, false>(as_const(p.dx), as_const(p.dy), j0, j1, qx, qy, top, tix);
-    store_partial<K>(top[0], p, seg, qi[0], part);
+    double Sw = 0.0, Swz = 0.0;
+    const bool covered = knn_maybe_speculative<K>(p, j0, j1, qx[0], qy[0], top[0], Sw, Swz);
+    store_partial<K>(top[0], p, seg, qi[0], ws.part);
+    if (p.spec_power) {
+        if (lane_id() == 0) ws.seg_ok[(int64_t)seg * sp.tiles + tile] = covered;
+        if (covered && qi[0] < p.n) {
+            ws.psum[((int64_t)seg * 2 + 0) * p.n + qi[0]] = Sw;
+            ws.psum[((int64_t)seg * 2 + 1) * p.n + qi[0]] = Swz;
+        }
+    }
 }
 
 // Merge the segment lists of each query (in segment order), then alpha.
+// A wave here is one 64-query tile.  With p.spec_power set it also decides
+// whether the tile's speculative sums stand: every segment formed them and
+// pass 2 would take the unscaled loop of that power in every lane (the
+// choice scan_wsum_any makes).
 template <int K>
 __global__ __launch_bounds__(kGroupSize) void aidw_f32_knn_merge(ProblemF32 p, SplitPlan sp,
-                                                                 const float* __restrict__ part,
-                                                                 float* __restrict__ qpar) {
+                                                                 SplitWorkspace ws) {
     const int q = blockIdx.x * kGroupSize + threadIdx.x;
     if (q >= p.n) return;
-    merge_tile<K>(p, sp, part, qpar, q);
+    merge_tile<K>(p, sp, ws.part, ws.qpar, q);
+    if (p.spec_power) {
+        const int tile = q / kWaveSize;
+        bool ok = (int)ws.qpar[3 * p.n + q] == p.spec_power && unscaled_ok(ws.qpar[p.n + q], p.zmax);
+        for (int seg = 0; seg < sp.segments; ++seg) ok &= ws.seg_ok[(int64_t)seg * sp.tiles + tile] != 0;
+        ok = __all(ok);
+        if (lane_id() == 0) ws.tile_ok[tile] = ok;
+    }
 }
 
 // Per-segment weighted sums: psum[(seg * 2 + {0: sum w, 1: sum w z}) * n + q].
+// Items of tiles whose speculative sums stand (tile_ok, may be null) have
+// nothing to do.
 __global__ __launch_bounds__(kGroupSize) void aidw_f32_wsum_part(ProblemF32 p, SplitPlan sp,
                                                                  const float* __restrict__ qpar,
-                                                                 double* __restrict__ psum) {
+                                                                 double* __restrict__ psum,
+                                                                 const int* __restrict__ tile_ok) {
     const int wave = wave_id();
     const int seg = wave / sp.tiles;
     const int tile = wave - seg * sp.tiles;
     if (seg >= sp.segments) return;
+    if (tile_ok && tile_ok[tile]) return;
     const int j0 = seg * sp.seg_len;
     const int j1 = seg_end(p.m, j0, sp.seg_len);
     int qi[1];
@@ -870,8 +927,16 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_wsum_reduce(ProblemF32 p,
 // Segments are whole 16-point batches of at least kDeferMinSegment points.
 constexpr int kDeferMinSegment = 2048;
 
+// At least ceil(m / kDeferL2Segment) segments (at most kDeferMaxL2Segments),
+// so that when many tiles fail the waves resident together read one
+// segment of about 1.5 MB of x, y, z that stays in the XCD's L2 (as the
+// grid mode's pass 2 does).
+constexpr int kDeferL2Segment = 131072;
+constexpr int kDeferMaxL2Segments = 8;
+
 __device__ __forceinline__ void defer_plan(int m, int count, int target, int& segs, int& seg_len) {
     int want = count > 0 ? (target + count - 1) / count : 1;
+    want = max(want, min(kDeferMaxL2Segments, (m + kDeferL2Segment - 1) / kDeferL2Segment));
     want = max(1, min(want, m / kDeferMinSegment));
     seg_len = (int)(((int64_t)m + want - 1) / want);
     seg_len = (seg_len + 15) & ~15;
@@ -1064,11 +1129,11 @@ hipError_t launch_split(const ProblemF32& p, const SplitPlan& sp, const SplitWor
     const unsigned g_part = groups_for((int64_t)sp.tiles * sp.segments);
     const unsigned g_query = (unsigned)((p.n + kGroupSize - 1) / kGroupSize);
     hipLaunchKernelGGL((aidw_f32_knn_part<K>), dim3(g_part), dim3(kGroupSize), 0, stream, p, sp,
-                       ws.part);
+                       ws);
     hipLaunchKernelGGL((aidw_f32_knn_merge<K>), dim3(g_query), dim3(kGroupSize), 0, stream, p, sp,
-                       ws.part, ws.qpar);
+                       ws);
     hipLaunchKernelGGL(aidw_f32_wsum_part, dim3(g_part), dim3(kGroupSize), 0, stream, p, sp,
-                       ws.qpar, ws.psum);
+                       ws.qpar, ws.psum, p.spec_power ? ws.tile_ok : nullptr);
     hipLaunchKernelGGL(aidw_f32_wsum_reduce, dim3(g_query), dim3(kGroupSize), 0, stream, p, sp,
                        ws.psum);
     return hipGetLastError();
@@ -1144,9 +1209,10 @@ size_t spec_workspace_bytes(int64_t n, int target, DeferWorkspace* ws, char* bas
     const int64_t tiles = (n + kWaveSize - 1) / kWaveSize;
     const size_t a = 256;
     auto up = [&](size_t v) { return (v + a - 1) / a * a; };
-    // count * segments < target + count <= target + tiles items
+    // count * segments <= max(target + count, kDeferMaxL2Segments * count) items
+    const int64_t items = std::max<int64_t>(target + tiles, kDeferMaxL2Segments * tiles);
     const size_t sizes[4] = {sizeof(int), sizeof(int) * (size_t)tiles, 4 * sizeof(float) * (size_t)n,
-                             2 * sizeof(double) * (size_t)kWaveSize * (size_t)(target + tiles)};
+                             2 * sizeof(double) * (size_t)kWaveSize * (size_t)items};
     size_t off[4], bytes = 0;
     for (int i = 0; i < 4; ++i) {
         off[i] = bytes;
@@ -1186,7 +1252,7 @@ hipError_t launch_aidw_f32_pass2(const ProblemF32& p, SplitPlan sp, const float*
     if (p.n <= 0) return hipSuccess;
     sp.tiles = (int)((p.n + kWaveSize - 1) / kWaveSize);
     hipLaunchKernelGGL(aidw_f32_wsum_part, dim3(groups_for((int64_t)sp.segments * sp.tiles)),
-                       dim3(kGroupSize), 0, stream, p, sp, qpar, psum);
+                       dim3(kGroupSize), 0, stream, p, sp, qpar, psum, (const int*)nullptr);
     hipLaunchKernelGGL(aidw_f32_wsum_reduce, dim3((unsigned)((p.n + kGroupSize - 1) / kGroupSize)),
                        dim3(kGroupSize), 0, stream, p, sp, psum);
     return hipGetLastError();

@@ -227,15 +227,15 @@ def _plan(ctx, torch, inst, n, levels):
 
 def test_automatic_split_boundaries(ctx, torch):
     """The automatic plan splits m below two rounds of 64-query tiles (8
-    waves per SIMD) for the two-pass kernel, and below half a round when the
-    speculative single pass applies (alpha_5 whole)."""
+    waves per SIMD): the unsplit launch is the speculative single pass when
+    alpha_5 is whole and the two-pass kernel otherwise; the split kernels
+    speculate per segment."""
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     rnd = cus * 4 * 8 * 64  # queries in one round of tiles
     inst = workloads.paper_scale(m=1 << 14, n=2 * rnd, seed=78, k=15)
     whole5, frac5 = (1, 2, 3, 4, 5), (1, 2, 3, 4, 4.5)
     assert "aidw_f32_fused_spec<16>" in _plan(ctx, torch, inst, 2 * rnd, whole5)
-    assert "aidw_f32_fused_spec<16>" in _plan(ctx, torch, inst, rnd // 2, whole5)
-    assert "aidw_f32_knn_part<16>" in _plan(ctx, torch, inst, rnd // 2 - 64, whole5)
+    assert "aidw_f32_knn_part<16>" in _plan(ctx, torch, inst, 2 * rnd - 64, whole5)
     assert "aidw_f32_fused<16, 1, false>" in _plan(ctx, torch, inst, 2 * rnd, frac5)
     assert "aidw_f32_knn_part<16>" in _plan(ctx, torch, inst, 2 * rnd - 64, frac5)
 
@@ -249,7 +249,7 @@ def test_automatic_split_boundary(ctx, torch, levels):
 
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     rnd = cus * 4 * 8 * 64
-    n = rnd // 2 if levels[4] == int(levels[4]) else 2 * rnd
+    n = 2 * rnd
     inst = workloads.paper_scale(m=1 << 16, n=n, seed=77, k=15)
     inst.levels = levels
     below = copy.copy(inst)
