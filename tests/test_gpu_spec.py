@@ -156,3 +156,47 @@ def test_noalloc_takes_the_same_path(ctx, torch):
         torch.cuda.synchronize()
         outs.append(out.cpu().numpy())
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("segments", [3, 8])
+def test_split_speculation_is_bit_identical(ctx, segments):
+    # in the split kernels a pass-1 item's speculative sums are the sums its
+    # pass-2 item would write, so the output does not depend on which tiles
+    # kept the speculation
+    inst = workloads.dense_patch(m=20000, n=2500, seed=26 + segments, k=15)
+    data_xy, data_z, query_xy = aidw.to_device(inst)
+    res = []
+    for speculate in (0, 1):
+        ctx.set_tuning(0, 0, segments, speculate)
+        try:
+            res.append(tuple(t.cpu().numpy() for t in ctx.interpolate(
+                data_xy, data_z, query_xy, inst.k, inst.levels, inst.R_min, inst.R_max, inst.area,
+                diag=True, knn=False)[:3]))
+        finally:
+            ctx.set_tuning(0)
+    (o0, r0, a0), (o1, r1, a1) = res
+    assert np.array_equal(r0, r1) and np.array_equal(a0, a1)
+    assert np.array_equal(o0, o1)
+    err, a_ref = oracle_check(inst, o0)
+    say("split %d: tiles off alpha_5 %d of %d, err %.3e" % (segments, failing_tiles(a_ref),
+                                                           -(-inst.n // 64), err))
+    assert 0 < failing_tiles(a_ref) < -(-inst.n // 64)
+    assert err <= TOL_F32
+
+
+def test_speculate_off_gives_the_two_pass_kernel(ctx, ctx_det, torch):
+    inst = workloads.dense_patch(m=8192, n=1500, seed=31, k=15)
+    data_xy, data_z, query_xy = aidw.to_device(inst)
+    out = torch.empty(inst.n, dtype=torch.float32, device="cuda")
+    ctx.set_tuning(0, 0, 1, 1)
+    try:
+        p = ctx.problem(data_xy, data_z, query_xy, inst.k, out, inst.levels, inst.R_min,
+                        inst.R_max, inst.area)
+        assert "aidw_f32_fused<16, 1, false>" in aidw.aidw_describe_launch(ctx.h, p)
+        ctx.bind_current_stream()
+        aidw.check(aidw.aidw_interpolate_ex(ctx.h, p))
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_tuning(0)
+    two_pass, _, _ = run(ctx_det, inst)
+    assert np.array_equal(out.cpu().numpy(), two_pass)
