@@ -229,8 +229,10 @@ def main():
     if args.ablation:
         result["ablation"] = bench_ablation(ctx, torch, aidw, workloads)
     elif not args.no_ablation:
+        # the 1000K row of Table 1 in FP32, the FP64 designs at 100K (an FP64
+        # design takes about 7 s at 1000K)
         result["ablation"] = bench_ablation(ctx, torch, aidw, workloads, sizes=(1024000,),
-                                            with_fp64=False)
+                                            fp64_sizes=(102400,))
     if not args.no_batch:
         result["batched"] = bench_batched(ctx, torch, aidw, workloads)
     if not args.no_serve:
@@ -263,23 +265,28 @@ def main():
 
 
 def bench_ablation(ctx, torch, aidw, workloads, sizes=(10240, 51200, 102400, 512000, 1024000),
-                   with_fp64=True):
+                   fp64_sizes=(10240, 51200, 102400, 512000, 1024000), with_fp32=True):
     """The paper's Table 1 axes on this GPU: m = n = N points in a square,
-    every data-access design and layout, the production launch and the plain
-    FP64 kernel (FP32 against FP64, as the paper's Table 1 does).  Times
-    are kernel-only (HIP events) and end to end (pinned host -> device copy of
-    the inputs, kernel, device -> host copy of the output), as in Sec. 4."""
-    designs = [("production", None, None)] + [
-        ("%s_%s" % (a, l), ai, li)
-        for ai, a in enumerate(["scalar", "tiled", "naive"])
-        for li, l in enumerate(["soa", "aoas"])] + ([("plain_fp64", None, None)] if with_fp64 else [])
+    every data-access design and layout, in FP32-scaled arithmetic (with the
+    production launch beside them) and in plain FP64 (the paper's Sec. 4.2
+    experiment).  Times are kernel-only (HIP events) and end to end (pinned
+    host -> device copy of the inputs, kernel, device -> host copy of the
+    output), as in Sec. 4."""
+    designs = [("%s_%s" % (a, l), ai, li)
+               for ai, a in enumerate(["scalar", "tiled", "naive"])
+               for li, l in enumerate(["soa", "aoas"])]
     rows = []
-    for N in sizes:
+    for N in sorted(set(sizes) | set(fp64_sizes)):
+        runs = []
+        if with_fp32 and N in sizes:
+            runs += [("production", None, None, False)] + [(d, a, l, False) for d, a, l in designs]
+        if N in fp64_sizes:
+            runs += [("fp64_" + d, a, l, True) for d, a, l in designs]
         inst = workloads.paper_scale(m=N, n=N, seed=7)
         inst64 = workloads.paper_scale(m=N, n=N, seed=7, dtype=np.float64)
-        for name, acc, lay in designs:
+        for name, acc, lay, f64 in runs:
             print("bench: ablation N=%d %s" % (N, name), file=sys.stderr, flush=True)
-            src = inst64 if name == "plain_fp64" else inst
+            src = inst64 if f64 else inst
             host = [torch.from_numpy(a).pin_memory() for a in
                     (src.data_xy(), src.data_z.copy(), src.query_xy())]
             out_h = torch.empty(N, dtype=host[0].dtype).pin_memory()
@@ -312,7 +319,8 @@ def bench_ablation(ctx, torch, aidw, workloads, sizes=(10240, 51200, 102400, 512
                          "end_to_end_ms": e[0].elapsed_time(e[3]),
                          "pair_evals_per_s": 2.0 * N * N / (kern * 1e-3)})
     return {"workload": "m = n = N uniform points in [0, 1000]^2, k = 15 (N as in the paper's "
-                        "Table 1, 1K = 1024)", "rows": rows}
+                        "Table 1, 1K = 1024); designs: scalar / LDS-tiled / naive loads x SoA / "
+                        "AoaS, FP32-scaled and plain FP64", "rows": rows}
 
 
 def _time_ms(torch, run, reps):

@@ -211,8 +211,8 @@ aidw_status aidw_idw(aidw_t h, const aidw_problem* p, double power);
 
 /* Data-access designs, for comparing the paper's implementation choices on
  * this GPU (Sec. 3.1.3 data layouts; Sec. 3.2 naive and tiled versions).
- * Every variant does the FP32-scaled arithmetic of aidw_interpolate_ex, one
- * query per lane, and differs only in how data points reach the lanes. */
+ * Every variant of a precision does the same arithmetic and differs only in
+ * how data points reach the lanes. */
 typedef enum aidw_access {
     AIDW_ACCESS_SCALAR = 0,  /* wave-uniform scalar loads (the production design) */
     AIDW_ACCESS_TILED = 1,   /* 256-point tiles staged in LDS per workgroup */
@@ -220,12 +220,16 @@ typedef enum aidw_access {
 } aidw_access;
 typedef enum aidw_layout {
     AIDW_LAYOUT_SOA = 0,   /* x[], y[], z[] as given */
-    AIDW_LAYOUT_AOAS = 1   /* {x, y, z, pad} per point, 16-byte aligned, packed by the
-                              library into its workspace (16 m bytes) */
+    AIDW_LAYOUT_AOAS = 1   /* {x, y, z, pad} per point, aligned to its size, packed by
+                              the library into its workspace */
 } aidw_layout;
 
-/* One FP32-scaled problem with a given access design and layout.  Fields
- * as in aidw_interpolate_ex (knn_idx must be NULL). */
+/* One problem with a given access design and layout.  Fields as in
+ * aidw_interpolate_ex.  FP32-scaled variants do the arithmetic of
+ * aidw_interpolate_ex with one query per lane (knn_idx must be NULL); FP64
+ * variants are bit-identical to the plain FP64 kernel (knn_idx allowed).
+ * AoaS needs 16 m (FP32) or 32 m (FP64) bytes of library workspace.
+ * AIDW_FLAG_GRID_KNN is rejected (AIDW_EINVAL). */
 aidw_status aidw_interpolate_variant(aidw_t h, const aidw_problem* p, aidw_access access,
                                      aidw_layout layout);
 

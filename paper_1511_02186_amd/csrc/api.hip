@@ -693,26 +693,25 @@ aidw_status aidw_interpolate_variant(aidw_t h, const aidw_problem* p, aidw_acces
     if (!h) return fail(AIDW_EINVAL, "handle is NULL");
     aidw_status st = validate(p);
     if (st != AIDW_OK) return st;
-    if (p->precision != AIDW_FP32_SCALED)
-        return fail(AIDW_EINVAL, "access variants are FP32-scaled only");
-    if (p->knn_idx) return fail(AIDW_EINVAL, "access variants do not produce knn_idx");
+    if (p->flags & AIDW_FLAG_GRID_KNN) return fail(AIDW_EINVAL, "access variants scan all points");
+    if (p->precision == AIDW_FP32_SCALED && p->knn_idx)
+        return fail(AIDW_EINVAL, "FP32-scaled access variants do not produce knn_idx");
     if ((int)access < 0 || (int)access > 2) return fail(AIDW_EINVAL, "unknown access %d", (int)access);
     if ((int)layout < 0 || (int)layout > 1) return fail(AIDW_EINVAL, "unknown layout %d", (int)layout);
     if (p->n == 0) return AIDW_OK;
-    float4* aos = nullptr;
+    const bool f64 = p->precision == AIDW_FP64;
+    void* aos = nullptr;
     if (layout == AIDW_LAYOUT_AOAS) {
-        st = ensure_workspace(h, sizeof(float4) * (size_t)p->m);
+        st = ensure_workspace(h, (f64 ? sizeof(double4) : sizeof(float4)) * (size_t)p->m);
         if (st != AIDW_OK) return st;
-        aos = static_cast<float4*>(h->workspace);
+        aos = h->workspace;
     }
-    hipError_t e = aidw::launch_aidw_f32_variant(problem_f32(p), (int)access, (int)layout, aos,
-                                                 h->stream);
-    if (e != hipSuccess) return hip_fail(e, "kernel launch");
-    if (!(p->flags & AIDW_FLAG_ASYNC)) {
-        e = hipStreamSynchronize(h->stream);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    }
-    return AIDW_OK;
+    hipError_t e =
+        f64 ? aidw::launch_aidw_f64_variant(problem_f64(p), (int)access, (int)layout,
+                                            static_cast<double4*>(aos), h->stream)
+            : aidw::launch_aidw_f32_variant(problem_f32(p), (int)access, (int)layout,
+                                            static_cast<float4*>(aos), h->stream);
+    return finish_launch(h, p, e);
 }
 
 aidw_status aidw_set_tuning(aidw_t h, const aidw_tuning* t) {

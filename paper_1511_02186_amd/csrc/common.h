@@ -221,5 +221,9 @@ hipError_t launch_aidw_f64(const ProblemF64& p, hipStream_t stream);
 // (0 SoA, 1 AoaS packed into `aos`, m float4), same arithmetic.
 hipError_t launch_aidw_f32_variant(const ProblemF32& p, int access, int layout, float4* aos,
                                    hipStream_t stream);
+// The same designs for the plain FP64 kernel (access 0 with layout 0 is that
+// kernel), `aos` m double4; bit-identical to it.
+hipError_t launch_aidw_f64_variant(const ProblemF64& p, int access, int layout, double4* aos,
+                                   hipStream_t stream);
 
 }  // namespace aidw

@@ -169,7 +169,157 @@ hipError_t launch_serve_k(const ProblemF64* jobs, const ServeItem* items, int n_
     return hipGetLastError();
 }
 
+// ---- data-access variants (the paper's naive and tiled versions in FP64) ------
+// The arithmetic of f64_query point by point in the same order -- the k
+// nearest by (d^2, index), pass 2 Neumaier-summed in data order -- so every
+// variant equals the plain kernel bit for bit; only the way a data point
+// reaches the lanes differs: access 0 scalar loads (as the plain kernel),
+// 1 LDS tiles of kTile64 points staged by the workgroup with coalesced loads,
+// 2 one vector load per lane and point (the address is lane-dependent in
+// form: vary = 0 at run time but unknown to the compiler).  Layout 0 reads
+// x[], y[], z[]; layout 1 one 32-byte {x, y, z, pad} per point, packed by
+// the library.
+constexpr int kTile64 = kGroupSize;
+
+struct D4 {
+    double x, y, z, w;
+};
+
+template <int ACCESS, int LAYOUT>
+__device__ __forceinline__ D4 fetch64(const ProblemF64& p, const double4* __restrict__ aos, int j,
+                                      int vary) {
+    if constexpr (ACCESS == 0) {
+        if constexpr (LAYOUT == 1) {
+            const cptr64 a = (cptr64)aos + 4 * (int64_t)j;
+            return D4{a[0], a[1], a[2], 0.0};
+        } else {
+            return D4{((cptr64)p.dx)[j], ((cptr64)p.dy)[j], ((cptr64)p.dz)[j], 0.0};
+        }
+    } else {
+        const int i = ACCESS == 2 ? j + ((int)threadIdx.x & vary) : j;
+        if constexpr (LAYOUT == 1) {
+            const double4 v = aos[i];
+            return D4{v.x, v.y, v.z, 0.0};
+        } else {
+            return D4{p.dx[i], p.dy[i], p.dz[i], 0.0};
+        }
+    }
+}
+
+template <int K, int ACCESS, int LAYOUT, bool TRACK>
+__global__ __launch_bounds__(kGroupSize) void aidw_f64_variant(ProblemF64 p,
+                                                               const double4* __restrict__ aos,
+                                                               int vary) {
+    __shared__ D4 tile[kTile64];
+    const int qi = blockIdx.x * kGroupSize + threadIdx.x;
+    const int c = qi < p.n ? qi : p.n - 1;
+    const double qx = p.qx[c], qy = p.qy[c];
+    const int m = p.m;
+    const int pad = K - p.ap.k;
+    double top[K];
+    int tix[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        top[i] = i < pad ? -INFINITY : INFINITY;
+        tix[i] = -1;
+    }
+    // the whole workgroup walks the data in tiles (ACCESS 1) or each lane on
+    // its own (ACCESS 0, 2); `visit` sees every point once, in data order
+    auto walk = [&](auto&& visit) {
+        if constexpr (ACCESS == 1) {
+            for (int base = 0; base < m; base += kTile64) {
+                const int cnt = min(kTile64, m - base);
+                if ((int)threadIdx.x < cnt)
+                    tile[threadIdx.x] = fetch64<1, LAYOUT>(p, aos, base + threadIdx.x, 0);
+                __syncthreads();
+                for (int j = 0; j < cnt; ++j) visit(tile[j], base + j);
+                __syncthreads();
+            }
+        } else {
+            for (int j = 0; j < m; ++j) visit(fetch64<ACCESS, LAYOUT>(p, aos, j, vary), j);
+        }
+    };
+    walk([&](const D4& pt, int j) {
+        const double d2 = sqdist64(qx, qy, pt.x, pt.y);
+        if (d2 < top[K - 1]) list_insert_idx<K, double>(top, tix, d2, j);
+    });
+    double r_obs;
+    const double al = alpha_from_list<K, double>(top, p.ap, r_obs);
+    const double d2min = list_min<K, double>(top, p.ap.k);
+    const bool coincident = (d2min == 0.0) && (al > 0.0);
+    const double e = -0.5 * al;
+    Neumaier num, den;
+    walk([&](const D4& pt, int) {
+        const double d2 = sqdist64(qx, qy, pt.x, pt.y);
+        const double w = coincident ? (d2 == 0.0 ? 1.0 : 0.0) : pow(d2, e);
+        num.add(w * pt.z);
+        den.add(w);
+    });
+    if (qi < p.n) {
+        p.out[qi] = num.value() / den.value();
+        if (p.r_obs) p.r_obs[qi] = r_obs;
+        if (p.alpha) p.alpha[qi] = al;
+        if constexpr (TRACK) {
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                if (i >= pad) p.knn[(int64_t)qi * p.ap.k + (i - pad)] = tix[i];
+        }
+    }
+}
+
+__global__ void pack_aoas64(const double* __restrict__ x, const double* __restrict__ y,
+                            const double* __restrict__ z, int m, double4* __restrict__ aos) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) aos[i] = make_double4(x[i], y[i], z[i], 0.0);
+}
+
+template <int K, int ACCESS, int LAYOUT>
+hipError_t launch_v64(const ProblemF64& p, const double4* aos, hipStream_t s) {
+    const unsigned groups = (unsigned)((p.n + kGroupSize - 1) / kGroupSize);
+    if (p.knn)
+        hipLaunchKernelGGL((aidw_f64_variant<K, ACCESS, LAYOUT, true>), dim3(groups),
+                           dim3(kGroupSize), 0, s, p, aos, 0);
+    else
+        hipLaunchKernelGGL((aidw_f64_variant<K, ACCESS, LAYOUT, false>), dim3(groups),
+                           dim3(kGroupSize), 0, s, p, aos, 0);
+    return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_vk64(const ProblemF64& p, int access, int layout, const double4* aos,
+                       hipStream_t s) {
+    switch (access * 2 + layout) {
+        case 0: return launch_k<K>(p, s);  // the plain kernel itself
+        case 1: return launch_v64<K, 0, 1>(p, aos, s);
+        case 2: return launch_v64<K, 1, 0>(p, aos, s);
+        case 3: return launch_v64<K, 1, 1>(p, aos, s);
+        case 4: return launch_v64<K, 2, 0>(p, aos, s);
+        case 5: return launch_v64<K, 2, 1>(p, aos, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_aidw_f64_variant(const ProblemF64& p, int access, int layout, double4* aos,
+                                   hipStream_t stream) {
+    if (p.n <= 0) return hipSuccess;
+    if (layout == 1) {
+        hipLaunchKernelGGL(pack_aoas64, dim3((unsigned)((p.m + 255) / 256)), dim3(256), 0, stream,
+                           p.dx, p.dy, p.dz, p.m, aos);
+    }
+    switch (k_bucket(p.ap.k)) {
+        case 4: return launch_vk64<4>(p, access, layout, aos, stream);
+        case 8: return launch_vk64<8>(p, access, layout, aos, stream);
+        case 10: return launch_vk64<10>(p, access, layout, aos, stream);
+        case 12: return launch_vk64<12>(p, access, layout, aos, stream);
+        case 16: return launch_vk64<16>(p, access, layout, aos, stream);
+        case 20: return launch_vk64<20>(p, access, layout, aos, stream);
+        case 24: return launch_vk64<24>(p, access, layout, aos, stream);
+        case 32: return launch_vk64<32>(p, access, layout, aos, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_aidw_f64_serve(const ProblemF64* jobs, const ServeItem* items, int n_items,
                                  int K, bool track, hipStream_t stream) {

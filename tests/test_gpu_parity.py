@@ -388,6 +388,31 @@ def test_access_variants_match_oracle(ctx, torch, access, layout, m, n, k):
     assert np.max(np.abs(alpha.cpu().numpy() - o_a)) <= 1e-5
 
 
+@pytest.mark.parametrize("access,layout", [(0, 1), (1, 0), (1, 1), (2, 0), (2, 1)])
+@pytest.mark.parametrize("m,n,k", [(700, 300, 10), (1537, 257, 15), (3, 65, 3)])
+def test_fp64_access_variants_equal_plain_kernel(ctx, torch, access, layout, m, n, k):
+    # the FP64 designs do the plain kernel's arithmetic in its order: equal
+    # to it bit for bit, to the oracle within 1e-12, with exact k-nearest sets
+    inst = workloads.clustered(m=m, n=n, seed=m + n + access, k=k, on_point=0.05,
+                               dtype=np.float64)
+    inst.area = max(inst.area, 1e-6) if m > 1 else 1.0
+    data_xy, data_z, query_xy = aidw.to_device(inst)
+    outs, knns = [], []
+    for acc, lay in ((0, 0), (access, layout)):
+        out = torch.full((inst.n,), float("nan"), dtype=torch.float64, device="cuda")
+        knn = torch.full((inst.n, inst.k), -7, dtype=torch.int32, device="cuda")
+        ctx.bind_current_stream()
+        p = ctx.problem(data_xy, data_z, query_xy, inst.k, out, inst.levels, inst.R_min,
+                        inst.R_max, inst.area, knn_idx=knn)
+        aidw.check(aidw.aidw_interpolate_variant(ctx.h, p, acc, lay))
+        outs.append(out.cpu().numpy())
+        knns.append(knn.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(knns[0], knns[1])
+    (o, _, _, o_knn), _ = ref(inst, diag=True)
+    assert np.max(np.abs(outs[1] - o) / np.maximum(np.abs(o), 1e-300)) <= TOL_F64
+    assert np.array_equal(np.sort(knns[1], axis=1), np.sort(o_knn, axis=1))
+
+
 # ---- whole powers: the unscaled weights only where FP32 holds them -----------------
 
 @pytest.mark.parametrize("coord_scale", [1e-7, 1.0, 1e3, 1e7])
