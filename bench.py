@@ -31,6 +31,7 @@ PEAK_FP32_TFLOPS = 157.3     # 256 CU x 2.4 GHz x 128 lanes x 2 (FMA)
 KERNEL_SOURCES = ["paper_1511_02186_amd/csrc/kernels_f32.hip",
                   "paper_1511_02186_amd/csrc/device_math.h",
                   "paper_1511_02186_amd/csrc/common.h",
+                  "paper_1511_02186_amd/csrc/kernels_order.hip",
                   "paper_1511_02186_amd/csrc/api.hip"]
 TRAFFIC_PROFILE = "profiles/aidw_f32_fused_spec_paper_scale_m1048576_n1048576.md"
 

@@ -50,7 +50,7 @@ extern "C" {
 #endif
 
 #define AIDW_VERSION_MAJOR 0
-#define AIDW_VERSION_MINOR 2
+#define AIDW_VERSION_MINOR 3
 
 /* Largest supported k (neighbours kept in registers per query). */
 #define AIDW_KMAX 32
@@ -177,6 +177,20 @@ aidw_status aidw_interpolate_ex(aidw_t h, const aidw_problem* p);
  * buffer. */
 aidw_status aidw_describe_launch(aidw_t h, const aidw_problem* p, char* buf, size_t cap);
 
+/* The spatial tile order that FP32-scaled launches use for these queries
+ * (aidw_tuning.query_order): order[pos] (device array of n int32) receives
+ * the index of the query at position pos, where positions 64 t .. 64 t + 63
+ * form tile t.  The queries (planar [2][n] FP32 device array) are sorted,
+ * stably, by the Morton code of their cell in a 2^b x 2^b grid over their
+ * bounding box, b = the least b >= 1 with 16 * 4^b >= n, at most 11 (cell
+ * index floor((x - x_min) * (2^b / (x_max - x_min))), in FP32, clamped to
+ * [0, 2^b - 1]; 0 where the extent is zero or not finite).  Launches keep the
+ * caller's order for a single tile (n <= 64); this function sorts any n >= 1.
+ * Independent of the handle's tuning.  May grow the handle's workspace; waits
+ * for the result.  Not part of the method: every query's result is its own in
+ * any order. */
+aidw_status aidw_query_order(aidw_t h, const void* query_xy, int64_t n, int32_t* order);
+
 /* For callers that cannot allocate device memory: code being captured into
  * a hipGraph, tight serving loops, harnesses that forbid hipMalloc.  Same
  * problem, results and errors as aidw_interpolate_ex, but the call
@@ -243,11 +257,26 @@ typedef struct aidw_tuning {
                                 automatically when the 64-query tiles give fewer
                                 than two rounds of 8 waves per SIMD */
     int speculate;           /* 0: when alpha_5 is a whole power in [1, 8], pass 1
-                                also forms the pass-2 sums of that power, which
-                                stand for every 64-query tile whose queries all end
-                                at alpha_5 (pass 2 then runs only for the other
-                                tiles; results equal to the two-pass sums, bit for
-                                bit for the tiles that kept them); 1: never */
+                                of the unsplit launch also forms the pass-2 sums of
+                                that power, which stand for every 64-query tile
+                                whose queries all end at alpha_5 (pass 2 then runs
+                                only for the other tiles; results equal to the
+                                two-pass sums, bit for bit for the tiles that kept
+                                them); 1: never; 2: as 0, and also per data segment
+                                in the split kernels (pays on data where nearly
+                                every tile ends at alpha_5, such as uniform points;
+                                costs on clustered data) */
+    int query_order;         /* which queries share a 64-query tile.  0: Morton order
+                                of their cells in the bounding box of the queries
+                                (neighbours share a tile: their k-nearest screens
+                                agree and, on clustered data, most tiles hold one
+                                alpha), when there is more than one tile and at
+                                least 1024 data points; 1: the caller's order;
+                                2: Morton order whenever there is more than one
+                                tile.  Each query's result is its own in every
+                                order; the grouping only sets which pass-2 loop a
+                                wave takes, so results agree to rounding.  Batched
+                                launches and deterministic handles use 0. */
 } aidw_tuning;
 
 /* Fix the launch shape used for FP32-scaled problems (NULL restores the

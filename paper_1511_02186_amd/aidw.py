@@ -75,7 +75,8 @@ class aidw_problem(ctypes.Structure):
 
 class aidw_tuning(ctypes.Structure):
     _fields_ = [("q_per_lane", ctypes.c_int), ("max_waves_per_simd", ctypes.c_int),
-                ("split_segments", ctypes.c_int), ("speculate", ctypes.c_int)]
+                ("split_segments", ctypes.c_int), ("speculate", ctypes.c_int),
+                ("query_order", ctypes.c_int)]
 
 
 class aidw_server_options(ctypes.Structure):
@@ -131,6 +132,8 @@ _SIGNATURES = {
                                         ctypes.c_void_p]),
     "aidw_interpolate_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem)]),
     "aidw_interpolate_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem)]),
+    "aidw_query_order": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_void_p]),
     "aidw_describe_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_problem),
                                             ctypes.c_char_p, ctypes.c_size_t]),
     "aidw_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aidw_tuning)]),
@@ -246,6 +249,12 @@ def aidw_interpolate_noalloc(h, problem: aidw_problem) -> int:
     return lib().aidw_interpolate_noalloc(h, ctypes.byref(problem))
 
 
+def aidw_query_order(h, query_xy, n: int, order) -> int:
+    """Tile order of n queries into order (device tensors or raw addresses)."""
+    ptr = lambda t: t if t is None or isinstance(t, int) else t.data_ptr()
+    return lib().aidw_query_order(h, ptr(query_xy), int(n), ptr(order))
+
+
 def aidw_describe_launch(h, problem: aidw_problem) -> str:
     """The kernels aidw_interpolate_ex would launch for `problem` (raises on error)."""
     buf = ctypes.create_string_buffer(1024)
@@ -277,10 +286,11 @@ def aidw_tune_load(h, path) -> int:
 
 
 def aidw_set_tuning(h, q_per_lane: int = 0, max_waves_per_simd: int = 0,
-                    split_segments: int = 0, speculate: int = 0) -> int:
-    if not q_per_lane and not max_waves_per_simd and not split_segments and not speculate:
+                    split_segments: int = 0, speculate: int = 0, query_order: int = 0) -> int:
+    if not (q_per_lane or max_waves_per_simd or split_segments or speculate or query_order):
         return lib().aidw_set_tuning(h, None)
-    t = aidw_tuning(int(q_per_lane), int(max_waves_per_simd), int(split_segments), int(speculate))
+    t = aidw_tuning(int(q_per_lane), int(max_waves_per_simd), int(split_segments), int(speculate),
+                    int(query_order))
     return lib().aidw_set_tuning(h, ctypes.byref(t))
 
 
@@ -440,8 +450,9 @@ class Context:
             pass
 
     def set_tuning(self, q_per_lane: int = 0, max_waves_per_simd: int = 0,
-                   split_segments: int = 0, speculate: int = 0):
-        check(aidw_set_tuning(self.h, q_per_lane, max_waves_per_simd, split_segments, speculate))
+                   split_segments: int = 0, speculate: int = 0, query_order: int = 0):
+        check(aidw_set_tuning(self.h, q_per_lane, max_waves_per_simd, split_segments, speculate,
+                              query_order))
 
     def bind_current_stream(self):
         import torch

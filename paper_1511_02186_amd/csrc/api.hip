@@ -358,11 +358,45 @@ struct F32Plan {
     aidw::LaunchF32 cfg;
     aidw::SplitPlan sp;
     bool spec;  // the speculative single pass, with pass 2 deferred for failed tiles
+    int order_bits;  // Morton bits per axis of the spatial tile order (0: caller's order)
 };
+
+// Fewer data points than this: the scans are short, and the order's seven
+// small launches would cost more than tile coherence saves.
+constexpr int64_t kOrderMinPoints = 1024;
+
+// Morton bits of the spatial tile order of a problem (0: the caller's
+// order).  mode: aidw_tuning.query_order (0 automatic, 1 never, 2 whenever
+// there is more than one tile).  Batched launches and deterministic handles
+// use the automatic choice.
+int order_bits_for(int mode, int64_t m, int64_t n) {
+    if (mode == 1 || (mode == 0 && m < kOrderMinPoints)) return 0;
+    return aidw::order_bits(n);
+}
+
+int order_passes(int bits) { return (2 * bits + 7) / 8; }
+int order_blocks(int64_t n) { return (int)((n + aidw::kOrderBlock - 1) / aidw::kOrderBlock); }
+
+// Order workspace of one problem (plan pl); with L given, laid out at base.
+size_t order_bytes(const F32Plan& pl, int64_t n, aidw::OrderLaunch* L, char* base) {
+    if (!pl.order_bits) return 0;
+    return aidw::order_workspace_bytes(n, order_blocks(n), 1, order_passes(pl.order_bits), L,
+                                       base);
+}
 
 // Speculative sums (the single pass, or per segment in the split kernels)
 // unless the handle is deterministic or its tuning turns them off.
 bool speculation_allowed(const aidw_ctx* h) { return !h->deterministic && h->tuning.speculate != 1; }
+
+// Speculative sums inside the split kernels only when the tuning asks for
+// them (speculate = 2).  There a tile that keeps them saves little over the
+// one-transcendental pass 2 it replaces (the distances, about 8 % of that
+// pass measured on uniform data), while a tile that forms them and then
+// misses alpha_5 pays a second pass 1; each segment decides from 1/32 of
+// its own points, so on clustered data many tiles do (m = n = 2^18
+// clustered: 25.9 ms with them, 21.7 ms without; uniform: 18.5 against
+// 19.8 ms).
+bool split_speculation(const aidw_ctx* h) { return speculation_allowed(h) && h->tuning.speculate == 2; }
 
 // Waves in one round of the device (8 per SIMD, 4 SIMDs per CU): what the
 // deferred pass 2 of the speculative launch aims to fill.
@@ -378,7 +412,8 @@ F32Plan plan_f32(const aidw_ctx* h, const aidw_problem* p) {
         t = tuned;
     F32Plan pl{aidw::LaunchF32{t.q_per_lane ? t.q_per_lane : default_q_per_lane(h, p->n),
                                t.max_waves_per_simd},
-               aidw::SplitPlan{1, (int)p->m, 0}, false};
+               aidw::SplitPlan{1, (int)p->m, 0}, false,
+               order_bits_for(h->deterministic ? 0 : h->tuning.query_order, p->m, p->n)};
     if (!p->knn_idx) pl.sp = split_plan_for(h, t, p->m, p->n);
     // The speculative single pass replaces the unsplit one-query-per-lane
     // kernel when alpha_5 is a whole power (a split problem speculates per
@@ -390,33 +425,49 @@ F32Plan plan_f32(const aidw_ctx* h, const aidw_problem* p) {
     return pl;
 }
 
-// Workspace of an FP32-scaled problem: max |z| in the first slot, then the
-// split-m buffers.
+// Workspace of an FP32-scaled problem: max |z| in the first slot, the tile
+// order, then the buffers of the speculative or the split launch.
 size_t f32_workspace_bytes(const aidw_ctx* h, const F32Plan& pl, const aidw_problem* p) {
-    if (pl.spec) return kZmaxSlot + aidw::spec_workspace_bytes(p->n, round_waves(h), nullptr, nullptr);
-    return kZmaxSlot +
+    const size_t head = kZmaxSlot + order_bytes(pl, p->n, nullptr, nullptr);
+    if (pl.spec) return head + aidw::spec_workspace_bytes(p->n, round_waves(h), nullptr, nullptr);
+    return head +
            (pl.sp.segments > 1 ? split_workspace_bytes(pl.sp, p->k, p->n, nullptr, nullptr) : 0);
+}
+
+// Queue the tile-order kernels of plan pl (order workspace at base) and
+// point q at the order.
+hipError_t launch_order(aidw_t h, const F32Plan& pl, aidw::ProblemF32& q, char* base) {
+    if (!pl.order_bits) return hipSuccess;
+    aidw::OrderLaunch L{};
+    order_bytes(pl, q.n, &L, base);
+    L.one = aidw::OrderSeg{q.qx, q.qy, q.n, 0, 0, order_blocks(q.n), pl.order_bits};
+    L.segments = 1;
+    L.blocks = order_blocks(q.n);
+    L.passes = order_passes(pl.order_bits);
+    q.order = L.order;
+    return aidw::launch_query_order(L, h->stream);
 }
 
 // Queue the max-|z| reduction and the FP32-scaled kernels of plan pl, with
 // the workspace at w (f32_workspace_bytes(h, pl, p) bytes, 256-byte aligned).
 hipError_t launch_f32(aidw_t h, const aidw_problem* p, const F32Plan& pl, char* w) {
     aidw::ProblemF32 q = problem_f32(p);
+    hipError_t e = launch_order(h, pl, q, w + kZmaxSlot);
+    if (e != hipSuccess) return e;
+    char* rest = w + kZmaxSlot + order_bytes(pl, p->n, nullptr, nullptr);
+    float* zmax = reinterpret_cast<float*>(w);
+    q.zmax = zmax;
     if (pl.spec) {
         aidw::DeferWorkspace dw{};
-        aidw::spec_workspace_bytes(p->n, round_waves(h), &dw, w + kZmaxSlot);
-        float* zmax = reinterpret_cast<float*>(w);
-        q.zmax = zmax;
-        hipError_t e = aidw::launch_abs_max(q.dz, q.m, zmax, h->stream, dw.count);
+        aidw::spec_workspace_bytes(p->n, round_waves(h), &dw, rest);
+        e = aidw::launch_abs_max(q.dz, q.m, zmax, h->stream, dw.count);
         if (e == hipSuccess) e = aidw::launch_aidw_f32_spec(q, dw, h->stream);
         return e;
     }
-    if (!speculation_allowed(h)) q.spec_power = 0;  // the split kernels speculate when it is set
+    if (!split_speculation(h)) q.spec_power = 0;  // the split kernels speculate when it is set
     aidw::SplitWorkspace ws{};
-    if (pl.sp.segments > 1) split_workspace_bytes(pl.sp, p->k, p->n, &ws, w + kZmaxSlot);
-    float* zmax = reinterpret_cast<float*>(w);
-    q.zmax = zmax;
-    hipError_t e = aidw::launch_abs_max(q.dz, q.m, zmax, h->stream);
+    if (pl.sp.segments > 1) split_workspace_bytes(pl.sp, p->k, p->n, &ws, rest);
+    e = aidw::launch_abs_max(q.dz, q.m, zmax, h->stream);
     if (e == hipSuccess) e = aidw::launch_aidw_f32(q, pl.cfg, &pl.sp, &ws, h->stream);
     return e;
 }
@@ -624,21 +675,49 @@ aidw_status aidw_describe_launch(aidw_t h, const aidw_problem* p, char* buf, siz
         d = "aidw_f64_plain" + k + (p->knn_idx ? ", true>" : ", false>");
     } else {
         const F32Plan pl = plan_f32(h, p);
+        if (pl.order_bits)
+            d = "aidw_order_bbox + (aidw_order_hist + aidw_order_scan + aidw_order_scatter) x " +
+                std::to_string(order_passes(pl.order_bits)) + " + ";
         if (pl.spec)
-            d = "aidw_abs_max + aidw_f32_fused_spec" + k + "> + aidw_f32_defer_part + "
-                "aidw_f32_defer_reduce";
+            d += "aidw_abs_max + aidw_f32_fused_spec" + k + "> + aidw_f32_defer_part + "
+                 "aidw_f32_defer_reduce";
         else if (pl.sp.segments > 1)
-            d = "aidw_abs_max + aidw_f32_knn_part" + k + "> + aidw_f32_knn_merge" + k +
-                "> + aidw_f32_wsum_part + aidw_f32_wsum_reduce (" +
-                std::to_string(pl.sp.segments) + " data segments)";
+            d += "aidw_abs_max + aidw_f32_knn_part" + k + "> + aidw_f32_knn_merge" + k +
+                 "> + aidw_f32_wsum_part + aidw_f32_wsum_reduce (" +
+                 std::to_string(pl.sp.segments) + " data segments)";
         else
-            d = "aidw_abs_max + aidw_f32_fused" + k + ", " + std::to_string(pl.cfg.q_per_lane) +
-                (p->knn_idx ? ", true>" : ", false>");
+            d += "aidw_abs_max + aidw_f32_fused" + k + ", " + std::to_string(pl.cfg.q_per_lane) +
+                 (p->knn_idx ? ", true>" : ", false>");
     }
     const size_t len = std::min(d.size(), cap - 1);
     memcpy(buf, d.data(), len);
     buf[len] = '\0';
     return AIDW_OK;
+}
+
+aidw_status aidw_query_order(aidw_t h, const void* query_xy, int64_t n, int32_t* order) {
+    ErrorScope es(h);
+    if (!h) return fail(AIDW_EINVAL, "handle is NULL");
+    if (n < 0 || n > AIDW_MAX_POINTS) return fail(AIDW_EINVAL, "n = %lld out of range", (long long)n);
+    if (n == 0) return AIDW_OK;
+    if (!query_xy || !order) return fail(AIDW_EINVAL, "query_xy or order is NULL");
+    const int bits = std::max(1, aidw::order_bits(n));
+    const int passes = order_passes(bits), blocks = order_blocks(n);
+    aidw_status st = ensure_workspace(h, aidw::order_workspace_bytes(n, blocks, 1, passes, nullptr,
+                                                                     nullptr));
+    if (st != AIDW_OK) return st;
+    aidw::OrderLaunch L{};
+    aidw::order_workspace_bytes(n, blocks, 1, passes, &L, static_cast<char*>(h->workspace));
+    const float* qx = static_cast<const float*>(query_xy);
+    L.one = aidw::OrderSeg{qx, qx + n, (int)n, 0, 0, blocks, bits};
+    L.segments = 1;
+    L.blocks = blocks;
+    L.passes = passes;
+    L.order = order;
+    hipError_t e = aidw::launch_query_order(L, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "order launch");
+    e = hipStreamSynchronize(h->stream);
+    return e == hipSuccess ? AIDW_OK : hip_fail(e, "hipStreamSynchronize");
 }
 
 aidw_status aidw_interpolate_noalloc(aidw_t h, const aidw_problem* p) {
@@ -656,6 +735,11 @@ aidw_status aidw_interpolate_noalloc(aidw_t h, const aidw_problem* p) {
     } else {
         F32Plan pl = plan_f32(h, p);
         const size_t cap = AIDW_NOALLOC_SCRATCH_BYTES;
+        // the tile order stays unless it alone would leave no room for the
+        // rest (about 20 n bytes: beyond 3 million queries)
+        if (pl.order_bits && kZmaxSlot + order_bytes(pl, p->n, nullptr, nullptr) + (1 << 20) > cap)
+            pl.order_bits = 0;
+        const size_t cap_rest = cap - order_bytes(pl, p->n, nullptr, nullptr);
         if (pl.spec && f32_workspace_bytes(h, pl, p) > cap) pl.spec = false;
         if (f32_workspace_bytes(h, pl, p) > cap) {
             if (h->tuning.split_segments > 1)
@@ -663,9 +747,9 @@ aidw_status aidw_interpolate_noalloc(aidw_t h, const aidw_problem* p) {
                             "split into %d segments the problem needs %zu bytes of scratch, "
                             "more than the %zu of the allocation-free entry point",
                             pl.sp.segments, f32_workspace_bytes(h, pl, p), cap);
-            pl.sp = fit_split(pl.sp, p->k, p->n, p->m, cap);
+            pl.sp = fit_split(pl.sp, p->k, p->n, p->m, cap_rest);
         }
-        if (f32_workspace_bytes(h, pl, p) > cap)  // unreachable: one segment needs 256 bytes
+        if (f32_workspace_bytes(h, pl, p) > cap)  // unreachable: one segment fits beside the order
             return fail(AIDW_ENOMEM, "scratch of %zu bytes exceeded", cap);
         e = launch_f32(h, p, pl, static_cast<char*>(h->scratch));
     }
@@ -726,7 +810,9 @@ aidw_status aidw_set_tuning(aidw_t h, const aidw_tuning* t) {
         return fail(AIDW_EINVAL, "q_per_lane must be 0, 1, 2 or 4");
     if (t->max_waves_per_simd < 0 || t->max_waves_per_simd > 8)
         return fail(AIDW_EINVAL, "max_waves_per_simd must be in [0, 8]");
-    if (t->speculate != 0 && t->speculate != 1) return fail(AIDW_EINVAL, "speculate must be 0 or 1");
+    if (t->speculate < 0 || t->speculate > 2) return fail(AIDW_EINVAL, "speculate must be 0, 1 or 2");
+    if (t->query_order < 0 || t->query_order > 2)
+        return fail(AIDW_EINVAL, "query_order must be 0, 1 or 2");
     h->tuning = *t;
     return AIDW_OK;
 }
@@ -790,18 +876,64 @@ aidw_status batch_build(aidw_t h, const aidw_problem* problems, int count, aidw_
                      [&](const aidw::BatchItem& x, const aidw::BatchItem& y) {
                          return probs[x.problem].m > probs[y.problem].m;
                      });
-    // device block: problems | items | max-|z| tasks | max-|z| slots
+    // Tile order of every problem with more than one tile (the automatic
+    // choice of a single launch), all sorted by one set of launches, each
+    // problem within its own range of positions.
+    std::vector<aidw::OrderSeg> segs;
+    std::vector<int> seg_problem, block_seg;
+    int64_t total = 0;
+    int max_bits = 0;
+    for (int i = 0; i < count; ++i) {
+        const int bits = order_bits_for(0, problems[i].m, problems[i].n);
+        if (!bits) continue;
+        const int nb = order_blocks(problems[i].n);
+        segs.push_back(aidw::OrderSeg{probs[i].qx, probs[i].qy, probs[i].n, (int)total,
+                                      (int)block_seg.size(), nb, bits});
+        seg_problem.push_back(i);
+        block_seg.insert(block_seg.end(), (size_t)nb, (int)segs.size() - 1);
+        total += problems[i].n;
+        max_bits = std::max(max_bits, bits);
+        if (total > (int64_t)INT32_MAX - aidw::kOrderBlock) {  // positions are 32-bit
+            segs.clear();
+            block_seg.clear();
+            break;
+        }
+    }
+    if (segs.empty()) total = 0;
+    const int passes = segs.empty() ? 0 : order_passes(max_bits);
+    // device block: problems | items | max-|z| tasks | max-|z| slots | order
+    // segments | sort block -> segment | order workspace
     const size_t a = 256;
     auto up = [&](size_t v) { return (v + a - 1) / a * a; };
     const size_t sz_p = up(sizeof(aidw::ProblemF32) * probs.size());
     const size_t sz_i = up(sizeof(aidw::BatchItem) * items.size());
     const size_t sz_t = up(sizeof(aidw::AbsMaxTask) * probs.size());
     const size_t o_t = sz_p + sz_i, o_z = o_t + sz_t;
-    const size_t bytes = o_z + up(sizeof(float) * probs.size());
+    const size_t o_s = o_z + up(sizeof(float) * probs.size());
+    const size_t o_b = o_s + up(sizeof(aidw::OrderSeg) * segs.size());
+    const size_t o_w = o_b + up(sizeof(int) * block_seg.size());
+    const size_t bytes =
+        o_w + (segs.empty() ? 0
+                            : aidw::order_workspace_bytes(total, (int)block_seg.size(),
+                                                          (int)segs.size(), passes, nullptr,
+                                                          nullptr));
     aidw_status st = device_alloc(h, bytes, &b->device_block);
     if (st != AIDW_OK) return st;
     b->device_bytes = bytes;
     char* base = static_cast<char*>(b->device_block);
+    aidw::OrderLaunch& L = b->launch.order;
+    L = aidw::OrderLaunch{};
+    if (!segs.empty()) {
+        aidw::order_workspace_bytes(total, (int)block_seg.size(), (int)segs.size(), passes, &L,
+                                    base + o_w);
+        L.table = reinterpret_cast<const aidw::OrderSeg*>(base + o_s);
+        L.block_seg = reinterpret_cast<const int*>(base + o_b);
+        L.segments = (int)segs.size();
+        L.blocks = (int)block_seg.size();
+        L.passes = passes;
+        for (size_t j = 0; j < segs.size(); ++j)
+            probs[seg_problem[j]].order = L.order + segs[j].base;
+    }
     float* zslots = reinterpret_cast<float*>(base + o_z);
     std::vector<aidw::AbsMaxTask> tasks(probs.size());
     for (size_t i = 0; i < probs.size(); ++i) {
@@ -815,6 +947,12 @@ aidw_status batch_build(aidw_t h, const aidw_problem* problems, int count, aidw_
                       hipMemcpyHostToDevice);
     if (e == hipSuccess && !tasks.empty())
         e = hipMemcpy(base + o_t, tasks.data(), sizeof(aidw::AbsMaxTask) * tasks.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !segs.empty())
+        e = hipMemcpy(base + o_s, segs.data(), sizeof(aidw::OrderSeg) * segs.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !block_seg.empty())
+        e = hipMemcpy(base + o_b, block_seg.data(), sizeof(int) * block_seg.size(),
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
     b->h = h;

@@ -45,6 +45,10 @@ struct ProblemF32 {
     // range (mu_R >= 0.9 in Eq. 5), used to stop speculating early.
     int spec_power;
     float spec_dist_sum;
+    // Optional tile order: position -> query index (null: the caller's
+    // order).  Tiles are 64 consecutive positions; per-query results go to
+    // the query's own index, internal per-query buffers are by position.
+    const int* order;
 };
 
 struct ProblemF64 {
@@ -107,6 +111,52 @@ struct DeferWorkspace {
     int target;    // waves the deferred pass 2 aims for (one round of the chip)
 };
 
+// ---- spatial order of the queries ----------------------------------------------
+// Queries are grouped into 64-query tiles in Morton order of their position
+// in the bounding box of the problem's queries (2^bits cells per axis), so
+// that a tile's queries are neighbours: their k-nearest screens trigger
+// together, and on clustered data most tiles hold queries of one alpha.  The
+// order is a stable LSD radix sort of the cell codes (8-bit digits), one or
+// more independent problems (segments) at a time.
+constexpr int kOrderThreads = 256;
+constexpr int kOrderItems = 16;
+constexpr int kOrderBlock = kOrderThreads * kOrderItems;  // queries per sort block
+
+struct OrderSeg {
+    const float* qx;
+    const float* qy;
+    int n;        // queries of this problem
+    int base;     // its first position in the concatenated order
+    int block0;   // its first sort block
+    int nblocks;  // ceil(n / kOrderBlock)
+    int bits;     // Morton bits per axis
+};
+
+// One order computation.  `table` (device array of `segments` entries, with
+// block_seg[b] the segment of sort block b) or, when table is null, the
+// single segment `one`.
+struct OrderLaunch {
+    const OrderSeg* table;
+    const int* block_seg;
+    OrderSeg one;
+    int segments;
+    int blocks;
+    int passes;          // ceil(2 * max bits / 8)
+    float4* bbox;        // [segments] x0, y0 and cells per unit in x and y
+    unsigned* keys[2];   // [total] keys between passes
+    int* vals[2];        // [total] query indices between passes
+    int* hist;           // [256 * blocks] digit counts, then scatter offsets
+    int* order;          // [total] result: position -> query index in its problem
+};
+
+// Morton bits per axis for n queries (0: no order for a single tile).
+int order_bits(int64_t n);
+// Bytes of the order workspace for `total` queries in `blocks` sort blocks
+// and `segments` problems; with L given, also lays it out at base.
+size_t order_workspace_bytes(int64_t total, int blocks, int segments, int passes, OrderLaunch* L,
+                             char* base);
+hipError_t launch_query_order(const OrderLaunch& L, hipStream_t stream);
+
 // One unit of batched work: 64 consecutive queries of one problem.
 struct BatchItem {
     int problem;
@@ -129,6 +179,7 @@ struct BatchLaunch {
     int n_tasks;
     int n_items;
     int K;                       // register bucket >= every problem's k
+    OrderLaunch order;           // tile order of every problem (order.blocks 0: none)
 };
 
 // ---- serving: one launch per scheduling tick --------------------------------

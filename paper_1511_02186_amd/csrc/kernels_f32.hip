@@ -621,23 +621,43 @@ __device__ __forceinline__ void scan_wsum_any(cptr X, cptr Y, cptr Z, int j0, in
     }
 }
 
+// The query at tile position `pos` (< p.n) of a problem.
+__device__ __forceinline__ int query_at(const ProblemF32& p, int pos) {
+    return p.order ? p.order[pos] : pos;
+}
+
+// A lane's queries of the tile starting at position `base`: positions qi
+// (lanes past the end load the last query and write nothing), the queries'
+// own indices qs (where their results go) and coordinates.
 template <int Q>
 __device__ __forceinline__ void load_queries(const ProblemF32& p, int base, int (&qi)[Q],
-                                             float (&qx)[Q], float (&qy)[Q]) {
+                                             int (&qs)[Q], float (&qx)[Q], float (&qy)[Q]) {
     const int lane = lane_id();
 #pragma unroll
     for (int s = 0; s < Q; ++s) {
         qi[s] = base + s * kWaveSize + lane;
-        const int c = qi[s] < p.n ? qi[s] : p.n - 1;
-        qx[s] = p.qx[c];
-        qy[s] = p.qy[c];
+        qs[s] = query_at(p, qi[s] < p.n ? qi[s] : p.n - 1);
+        qx[s] = p.qx[qs[s]];
+        qy[s] = p.qy[qs[s]];
     }
 }
 
 // ---- one tile of 64*Q queries, both passes over all m points ---------------
-// The alpha parameters of a problem, read through this pointer only after
-// pass 1 (see fused_tile).
+// A problem's fields that are needed only after a scan (the alpha
+// parameters, the output pointers) are read through a pointer to the
+// problem in the kernarg segment (or in the batch's table), laundered by an
+// empty asm at the point of use: loads of kernel arguments otherwise all go
+// to the kernel's entry, and their SGPRs stay live through the scans, which
+// costs resident waves (on gfx950 8 per SIMD up to 80 SGPRs, 7 up to about
+// 88, 6 beyond).
+typedef const __attribute__((address_space(4))) ProblemF32* prob_ptr;
 typedef const __attribute__((address_space(4))) AlphaParams* alpha_ptr;
+
+template <typename T>
+__device__ __forceinline__ T launder(T ptr) {
+    asm volatile("" : "+s"(ptr));
+    return ptr;
+}
 
 __device__ __forceinline__ AlphaParams load_alpha(alpha_ptr a) {
     AlphaParams ap;
@@ -651,19 +671,18 @@ __device__ __forceinline__ AlphaParams load_alpha(alpha_ptr a) {
 }
 
 // Pass-1 result of one lane's queries: the pass-2 terms (Eq. 2-6) and the
-// diagnostic outputs.  The alpha parameters (app points at p.ap) are read only
-// here, through an address laundered by an empty asm: loads of kernel
-// arguments otherwise all go to the kernel's entry, and these 17 SGPRs would
-// stay live through pass 1, which costs resident waves (on gfx950 8 per SIMD
-// up to 80 SGPRs, 7 up to about 88, 6 beyond).
+// diagnostic outputs (lp: the problem, read late).
 template <int K, int Q, bool TRACK>
-__device__ __forceinline__ void tile_powers(const ProblemF32& p, alpha_ptr app, const int (&qi)[Q],
+__device__ __forceinline__ void tile_powers(prob_ptr lp, const int (&qi)[Q], const int (&qs)[Q],
                                             const float (&top)[Q][K],
                                             const int (&tix)[TRACK ? Q : 1][TRACK ? K : 1],
                                             float (&na)[Q], float (&aL0)[Q], float (&d2min)[Q],
                                             int& ipw) {
-    asm volatile("" : "+s"(app));
-    const AlphaParams ap = load_alpha(app);
+    const prob_ptr L = launder(lp);
+    const AlphaParams ap = load_alpha(&L->ap);
+    const int n = L->n;
+    double* const r_obs_out = L->r_obs;
+    double* const alpha_out = L->alpha;
     const int pad = K - ap.k;
     ipw = 0;
 #pragma unroll
@@ -671,23 +690,24 @@ __device__ __forceinline__ void tile_powers(const ProblemF32& p, alpha_ptr app, 
         double r_obs, al;
         query_power<K>(top[s], ap, r_obs, al, na[s], aL0[s], d2min[s]);
         if (Q == 1) ipw = integer_power(al, d2min[s]);
-        if (qi[s] < p.n) {
-            if (p.r_obs) p.r_obs[qi[s]] = r_obs;
-            if (p.alpha) p.alpha[qi[s]] = al;
+        if (qi[s] < n) {
+            if (r_obs_out) r_obs_out[qs[s]] = r_obs;
+            if (alpha_out) alpha_out[qs[s]] = al;
             if constexpr (TRACK) {
+                int32_t* const knn = L->knn;
 #pragma unroll
                 for (int i = 0; i < K; ++i)
-                    if (i >= pad) p.knn[(int64_t)qi[s] * ap.k + (i - pad)] = tix[s][i];
+                    if (i >= pad) knn[(int64_t)qs[s] * ap.k + (i - pad)] = tix[s][i];
             }
         }
     }
 }
 
 template <int K, int Q, bool TRACK>
-__device__ __forceinline__ void fused_tile(const ProblemF32& p, alpha_ptr app, int base) {
-    int qi[Q];
+__device__ __forceinline__ void fused_tile(const ProblemF32& p, prob_ptr lp, int base) {
+    int qi[Q], qs[Q];
     float qx[Q], qy[Q];
-    load_queries<Q>(p, base, qi, qx, qy);
+    load_queries<Q>(p, base, qi, qs, qx, qy);
 
     float top[Q][K];
     int tix[TRACK ? Q : 1][TRACK ? K : 1];
@@ -696,7 +716,7 @@ __device__ __forceinline__ void fused_tile(const ProblemF32& p, alpha_ptr app, i
 
     float na[Q], aL0[Q], d2min[Q];
     int ipw;
-    tile_powers<K, Q, TRACK>(p, app, qi, top, tix, na, aL0, d2min, ipw);
+    tile_powers<K, Q, TRACK>(lp, qi, qs, top, tix, na, aL0, d2min, ipw);
 
     double Sw[Q], Swz[Q];
 #pragma unroll
@@ -704,10 +724,21 @@ __device__ __forceinline__ void fused_tile(const ProblemF32& p, alpha_ptr app, i
     scan_wsum_any<Q>(as_const(p.dx), as_const(p.dy), as_const(p.dz), 0, p.m, qx, qy, na, aL0, Sw,
                      Swz, ipw, sqrtf(d2min[0]), p.zmax);
 
+    const prob_ptr L = launder(lp);
+    float* const out = L->out;
+    const int n = L->n;
 #pragma unroll
     for (int s = 0; s < Q; ++s)
-        if (qi[s] < p.n) p.out[qi[s]] = (float)(Swz[s] / Sw[s]);
+        if (qi[s] < n) out[qs[s]] = (float)(Swz[s] / Sw[s]);
 }
+
+// Arguments of the speculative launch, one struct so that the kernel finds
+// the workspace at a known place in its kernarg segment.
+struct SpecArgs {
+    ProblemF32 p;
+    DeferWorkspace ws;
+};
+typedef const __attribute__((address_space(4))) SpecArgs* spec_args_ptr;
 
 // One tile of the speculative launch: pass 1 with the sums of p.spec_power
 // (knn_speculative), and the output where the speculation held in every lane;
@@ -716,52 +747,52 @@ __device__ __forceinline__ void fused_tile(const ProblemF32& p, alpha_ptr app, i
 // 80 SGPRs (8 waves per SIMD), and a failed tile's pass 2, split into data
 // segments, runs spread over the chip instead of as one long wave at the end.
 template <int K>
-__device__ __forceinline__ void spec_tile(const ProblemF32& p, alpha_ptr app, int tile,
-                                          const DeferWorkspace& ws) {
-    int qi[1];
+__device__ __forceinline__ void spec_tile(const ProblemF32& p, spec_args_ptr ka, int tile) {
+    int qi[1], qs[1];
     float qx[1], qy[1];
-    load_queries<1>(p, tile * kWaveSize, qi, qx, qy);
+    load_queries<1>(p, tile * kWaveSize, qi, qs, qx, qy);
     float top[1][K];
     int tix[1][1];
     init_lists<K, 1, false>(top, tix, p.ap.k);
     double Sw = 0.0, Swz = 0.0;
     const bool covered = knn_maybe_speculative<K>(p, 0, p.m, qx[0], qy[0], top[0], Sw, Swz);
-    const int spec = covered ? p.spec_power : 0;  // the power whose sums cover every point
 
     float na[1], aL0[1], d2min[1];
     int ipw;
-    tile_powers<K, 1, false>(p, app, qi, top, tix, na, aL0, d2min, ipw);
+    tile_powers<K, 1, false>(&ka->p, qi, qs, top, tix, na, aL0, d2min, ipw);
+    const spec_args_ptr L = launder(ka);
+    const int n = L->p.n;
+    // the power whose sums cover every point
+    const int spec = covered ? L->p.spec_power : 0;
     // the sums stand when pass 2 would take the unscaled loop of that same
     // power in this wave (the choice scan_wsum_any makes)
-    if (spec != 0 && __all(ipw == spec) && __all(unscaled_ok(aL0[0], p.zmax))) {
-        if (qi[0] < p.n) p.out[qi[0]] = (float)(Swz / Sw);
+    if (spec != 0 && __all(ipw == spec) && __all(unscaled_ok(aL0[0], L->p.zmax))) {
+        if (qi[0] < n) L->p.out[qs[0]] = (float)(Swz / Sw);
         return;
     }
-    if (qi[0] < p.n) {
-        ws.qpar[qi[0]] = na[0];
-        ws.qpar[p.n + qi[0]] = aL0[0];
-        ws.qpar[2 * p.n + qi[0]] = sqrtf(d2min[0]);
-        ws.qpar[3 * p.n + qi[0]] = (float)ipw;
+    float* const qpar = L->ws.qpar;
+    if (qi[0] < n) {
+        qpar[qi[0]] = na[0];
+        qpar[n + qi[0]] = aL0[0];
+        qpar[2 * n + qi[0]] = sqrtf(d2min[0]);
+        qpar[3 * n + qi[0]] = (float)ipw;
     }
-    if (lane_id() == 0) ws.list[atomicAdd(ws.count, 1)] = tile;
+    if (lane_id() == 0) L->ws.list[atomicAdd(L->ws.count, 1)] = tile;
 }
 
 template <int K, int Q, bool TRACK>
 __global__ __launch_bounds__(kGroupSize) void aidw_f32_fused(ProblemF32 p) {
     // p is the kernel's only explicit argument: it starts the kernarg segment
-    const ProblemF32 __attribute__((address_space(4)))* kp =
-        (const ProblemF32 __attribute__((address_space(4)))*)__builtin_amdgcn_kernarg_segment_ptr();
-    fused_tile<K, Q, TRACK>(p, &kp->ap, wave_id() * Q * kWaveSize);
+    fused_tile<K, Q, TRACK>(p, (prob_ptr)__builtin_amdgcn_kernarg_segment_ptr(),
+                            wave_id() * Q * kWaveSize);
 }
 
 // The speculative launch: one wave per tile (see spec_tile).
 template <int K>
-__global__ __launch_bounds__(kGroupSize) void aidw_f32_fused_spec(ProblemF32 p, DeferWorkspace ws) {
-    const ProblemF32 __attribute__((address_space(4)))* kp =
-        (const ProblemF32 __attribute__((address_space(4)))*)__builtin_amdgcn_kernarg_segment_ptr();
+__global__ __launch_bounds__(kGroupSize) void aidw_f32_fused_spec(SpecArgs a) {
     const int tile = wave_id();
-    if (tile * kWaveSize >= p.n) return;
-    spec_tile<K>(p, &kp->ap, tile, ws);
+    if (tile * kWaveSize >= a.p.n) return;
+    spec_tile<K>(a.p, (spec_args_ptr)__builtin_amdgcn_kernarg_segment_ptr(), tile);
 }
 
 // ---- batched: one wave per (problem, tile) item -------------------------------
@@ -772,7 +803,7 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_batch(const ProblemF32* _
     const int it = wave_id();
     if (it >= n_items) return;
     const BatchItem w = items[it];
-    fused_tile<K, 1, false>(probs[w.problem], (alpha_ptr)&probs[w.problem].ap, w.base);
+    fused_tile<K, 1, false>(probs[w.problem], (prob_ptr)&probs[w.problem], w.base);
 }
 
 // Per-segment k-nearest lists keep only the k real entries of each list,
@@ -813,8 +844,9 @@ __device__ __forceinline__ void merge_tile(const ProblemF32& p, const SplitPlan&
     qpar[p.n + q] = aL0;
     qpar[2 * p.n + q] = sqrtf(d2min);
     qpar[3 * p.n + q] = (float)integer_power(al, d2min);
-    if (p.r_obs) p.r_obs[q] = r_obs;
-    if (p.alpha) p.alpha[q] = al;
+    const int src = query_at(p, q);
+    if (p.r_obs) p.r_obs[src] = r_obs;
+    if (p.alpha) p.alpha[src] = al;
 }
 
 // ---- split-m ------------------------------------------------------------------
@@ -841,9 +873,9 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_knn_part(ProblemF32 p, Sp
     if (seg >= sp.segments) return;
     const int j0 = seg * sp.seg_len;
     const int j1 = seg_end(p.m, j0, sp.seg_len);
-    int qi[1];
+    int qi[1], qs[1];
     float qx[1], qy[1];
-    load_queries<1>(p, tile * kWaveSize, qi, qx, qy);
+    load_queries<1>(p, tile * kWaveSize, qi, qs, qx, qy);
     float top[1][K];
     int tix[1][1];
     init_lists<K, 1, false>(top, tix, p.ap.k);
@@ -893,9 +925,9 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_wsum_part(ProblemF32 p, S
     if (tile_ok && tile_ok[tile]) return;
     const int j0 = seg * sp.seg_len;
     const int j1 = seg_end(p.m, j0, sp.seg_len);
-    int qi[1];
+    int qi[1], qs[1];
     float qx[1], qy[1];
-    load_queries<1>(p, tile * kWaveSize, qi, qx, qy);
+    load_queries<1>(p, tile * kWaveSize, qi, qs, qx, qy);
     const int c = qi[0] < p.n ? qi[0] : p.n - 1;
     float na[1] = {qpar[c]}, aL0[1] = {qpar[p.n + c]};
     double Sw[1] = {0.0}, Swz[1] = {0.0};
@@ -916,7 +948,7 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_wsum_reduce(ProblemF32 p,
         Sw += psum[((int64_t)seg * 2 + 0) * p.n + q];
         Swz += psum[((int64_t)seg * 2 + 1) * p.n + q];
     }
-    p.out[q] = (float)(Swz / Sw);
+    p.out[query_at(p, q)] = (float)(Swz / Sw);
 }
 
 
@@ -957,9 +989,9 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_defer_part(ProblemF32 p, 
     const int tile = __builtin_amdgcn_readfirstlane(ws.list[pos]);
     const int j0 = seg * seg_len;
     const int j1 = seg_end(p.m, j0, seg_len);
-    int qi[1];
+    int qi[1], qs[1];
     float qx[1], qy[1];
-    load_queries<1>(p, tile * kWaveSize, qi, qx, qy);
+    load_queries<1>(p, tile * kWaveSize, qi, qs, qx, qy);
     const int c = qi[0] < p.n ? qi[0] : p.n - 1;
     const float* qp = ws.qpar;
     float na[1] = {qp[c]}, aL0[1] = {qp[p.n + c]};
@@ -989,7 +1021,7 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_defer_reduce(ProblemF32 p
         Sw += ws.psum[(int64_t)seg * 2 * stride + t];
         Swz += ws.psum[((int64_t)seg * 2 + 1) * stride + t];
     }
-    p.out[q] = (float)(Swz / Sw);
+    p.out[query_at(p, q)] = (float)(Swz / Sw);
 }
 
 // max |z| as the largest bit pattern of |z| (ordered like the values for
@@ -1042,14 +1074,14 @@ template <int K>
 __device__ __forceinline__ void serve_item(const ServeJob& J, const ServeItem& it) {
     const ProblemF32& p = J.p;
     if (it.phase == kServeFused) {
-        fused_tile<K, 1, false>(p, (alpha_ptr)&J.p.ap, it.tile * kWaveSize);
+        fused_tile<K, 1, false>(p, (prob_ptr)&J.p, it.tile * kWaveSize);
         return;
     }
     const int j0 = it.seg * J.sp.seg_len;
     const int j1 = seg_end(p.m, j0, J.sp.seg_len);
-    int qi[1];
+    int qi[1], qs[1];
     float qx[1], qy[1];
-    load_queries<1>(p, it.tile * kWaveSize, qi, qx, qy);
+    load_queries<1>(p, it.tile * kWaveSize, qi, qs, qx, qy);
     if (it.phase == kServeKnn) {
         float top[1][K];
         int tix[1][1];
@@ -1075,7 +1107,7 @@ __device__ __forceinline__ void serve_item(const ServeJob& J, const ServeItem& i
             sw += J.ws.psum[((int64_t)seg * 2 + 0) * p.n + qi[0]];
             swz += J.ws.psum[((int64_t)seg * 2 + 1) * p.n + qi[0]];
         }
-        p.out[qi[0]] = (float)(swz / sw);
+        p.out[qs[0]] = (float)(swz / sw);
     }
 }
 
@@ -1087,7 +1119,7 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_serve(const ServeJob* __r
     if (it >= n_items) return;
     const ServeItem w = items[it];
     if constexpr (TRACK)
-        fused_tile<K, 1, true>(jobs[w.job].p, (alpha_ptr)&jobs[w.job].p.ap,
+        fused_tile<K, 1, true>(jobs[w.job].p, (prob_ptr)&jobs[w.job].p,
                                w.tile * kWaveSize);  // jobs with knn_idx: unsplit
     else
         serve_item<K>(jobs[w.job], w);
@@ -1157,6 +1189,8 @@ hipError_t launch_batch_k(const BatchLaunch& b, hipStream_t stream) {
     if (b.n_tasks > 0)
         hipLaunchKernelGGL(aidw_abs_max_tasks, dim3((unsigned)b.n_tasks), dim3(256), 0, stream,
                            b.tasks);
+    const hipError_t e = launch_query_order(b.order, stream);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((aidw_f32_batch<K>), dim3(groups_for(b.n_items)), dim3(kGroupSize), 0,
                        stream, b.problems, b.items, b.n_items);
     return hipGetLastError();
@@ -1232,7 +1266,7 @@ template <int K>
 hipError_t launch_spec_k(const ProblemF32& p, const DeferWorkspace& ws, hipStream_t stream) {
     const int64_t tiles = (p.n + kWaveSize - 1) / kWaveSize;
     hipLaunchKernelGGL((aidw_f32_fused_spec<K>), dim3(groups_for(tiles)), dim3(kGroupSize), 0,
-                       stream, p, ws);
+                       stream, SpecArgs{p, ws});
     hipLaunchKernelGGL(aidw_f32_defer_part, dim3(groups_for(ws.target + tiles)), dim3(kGroupSize),
                        0, stream, p, ws);
     hipLaunchKernelGGL(aidw_f32_defer_reduce,

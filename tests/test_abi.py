@@ -57,7 +57,7 @@ def test_constants_match_header():
 
 def test_version_and_status_names():
     _lib_or_skip()
-    assert aidw.aidw_version() == (0 << 16) | 2
+    assert aidw.aidw_version() == (0 << 16) | 3
     assert aidw.status_name(aidw.AIDW_EINVAL) == "AIDW_EINVAL"
     assert aidw.status_name(aidw.AIDW_OK) == "AIDW_OK"
 

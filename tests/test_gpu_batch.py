@@ -170,6 +170,7 @@ def test_batched_config_512_instances(ctx, torch):
     worst = 0.0
     for d in devs:
         got = d.out.cpu().numpy()
+        assert not np.isnan(got).any(), d.inst.name  # every query written (NaN before)
         idx = np.sort(rng.choice(d.inst.n, 3, replace=False))
         o, scale = ref(d.inst, idx)
         worst = max(worst, rel_err(got[idx], o, scale).max())
@@ -181,9 +182,9 @@ def test_batched_config_512_instances(ctx, torch):
 
 # ---- split-m ---------------------------------------------------------------
 
-def _run(ctx, torch, inst, segments=0, diag=False):
+def _run(ctx, torch, inst, segments=0, diag=False, query_order=0):
     data_xy, data_z, query_xy = aidw.to_device(inst)
-    ctx.set_tuning(split_segments=segments)
+    ctx.set_tuning(split_segments=segments, query_order=query_order)
     try:
         # no knn_idx: asking for the indices would keep m unsplit
         r = ctx.interpolate(data_xy, data_z, query_xy, inst.k, inst.levels, inst.R_min,
@@ -255,8 +256,10 @@ def test_automatic_split_boundary(ctx, torch, levels):
     below = copy.copy(inst)
     below.query_x = np.ascontiguousarray(inst.query_x[: n - 64])
     below.query_y = np.ascontiguousarray(inst.query_y[: n - 64])
-    whole, r0, a0, _ = _run(ctx, torch, inst, diag=True)
-    split, r1, a1, _ = _run(ctx, torch, below, diag=True)
+    # in the caller's order, so that a query has the same wave mates on both
+    # sides (the spatial order of n - 64 queries groups them differently)
+    whole, r0, a0, _ = _run(ctx, torch, inst, diag=True, query_order=1)
+    split, r1, a1, _ = _run(ctx, torch, below, diag=True, query_order=1)
     assert np.array_equal(r0[: n - 64], r1)
     assert np.array_equal(a0[: n - 64], a1)
     assert np.allclose(split, whole[: n - 64], rtol=2e-7, atol=0)

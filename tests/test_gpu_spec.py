@@ -69,10 +69,31 @@ def oracle_check(inst, out, idx=None, levels=None):
     return err, a_ref
 
 
-def failing_tiles(alpha, power=5.0):
-    pad = (-alpha.size) % 64
-    a = np.concatenate([alpha, np.full(pad, power)])
-    return int(np.sum((a.reshape(-1, 64) != power).any(axis=1)))
+def tile_order(c, inst):
+    """The queries' tile order in these launches: the spatial order (as
+    aidw_query_order gives it) when there is more than one tile and at least
+    1024 data points, else the caller's order."""
+    import torch
+
+    if inst.m < 1024 or inst.n <= 64:
+        return np.arange(inst.n)
+    q = torch.from_numpy(inst.query_xy()).cuda()
+    order = torch.empty(inst.n, dtype=torch.int32, device="cuda")
+    c.bind_current_stream()
+    aidw.check(aidw.aidw_query_order(c.h, q, inst.n, order))
+    return order.cpu().numpy()
+
+
+def tile_flags(alpha, order, power=5.0):
+    """Per tile (64 consecutive positions of the order): some query off the power."""
+    a = alpha[order]
+    pad = (-a.size) % 64
+    a = np.concatenate([a, np.full(pad, power)])
+    return (a.reshape(-1, 64) != power).any(axis=1)
+
+
+def failing_tiles(alpha, order, power=5.0):
+    return int(np.sum(tile_flags(alpha, order, power)))
 
 
 def test_mixed_tiles_match_oracle_and_two_pass(ctx, ctx_det):
@@ -81,7 +102,8 @@ def test_mixed_tiles_match_oracle_and_two_pass(ctx, ctx_det):
     say("speculative pass: dense patch m=%d n=%d k=%d" % (inst.m, inst.n, inst.k))
     out, r_obs, alpha = run(ctx, inst)
     err, a_ref = oracle_check(inst, out)
-    fails = failing_tiles(a_ref)
+    order = tile_order(ctx, inst)
+    fails = failing_tiles(a_ref, order)
     say("  tiles off alpha_5: %d of %d, max rel err vs oracle %.3e" % (fails, -(-inst.n // 64), err))
     assert 0 < fails < -(-inst.n // 64)  # both kinds of tile are exercised
     assert err <= TOL_F32
@@ -90,7 +112,9 @@ def test_mixed_tiles_match_oracle_and_two_pass(ctx, ctx_det):
     assert np.array_equal(r_obs, r2) and np.array_equal(alpha, a2)
     # tiles that kept the speculation reproduce the two-pass sums bit for bit;
     # deferred tiles add their data segments in another grouping
-    keep = np.repeat(~(alpha.reshape(-1, 64) != 5.0).any(axis=1), 64)[: inst.n]
+    keep = np.zeros(inst.n, dtype=bool)
+    keep[order] = np.repeat(~tile_flags(alpha, order), 64)[: inst.n]
+    assert keep.any()
     assert np.array_equal(out[keep], out2[keep])
     scale = np.max(np.abs(out2))
     assert np.max(np.abs(out.astype(np.float64) - out2)) <= 1e-6 * scale
@@ -101,8 +125,8 @@ def test_every_tile_deferred(ctx):
     inst = workloads.clustered(m=8192, n=1000, seed=21, k=8)
     out, _, alpha = run(ctx, inst)
     err, a_ref = oracle_check(inst, out)
-    say("clustered k=8: tiles off alpha_5 %d of %d, err %.3e" % (failing_tiles(a_ref),
-                                                                  -(-inst.n // 64), err))
+    say("clustered k=8: tiles off alpha_5 %d of %d, err %.3e" % (
+        failing_tiles(a_ref, tile_order(ctx, inst)), -(-inst.n // 64), err))
     assert err <= TOL_F32
 
 
@@ -160,13 +184,13 @@ def test_noalloc_takes_the_same_path(ctx, torch):
 
 @pytest.mark.parametrize("segments", [3, 8])
 def test_split_speculation_is_bit_identical(ctx, segments):
-    # in the split kernels a pass-1 item's speculative sums are the sums its
-    # pass-2 item would write, so the output does not depend on which tiles
-    # kept the speculation
+    # in the split kernels (speculate = 2) a pass-1 item's speculative sums
+    # are the sums its pass-2 item would write, so the output does not depend
+    # on which tiles kept the speculation
     inst = workloads.dense_patch(m=20000, n=2500, seed=26 + segments, k=15)
     data_xy, data_z, query_xy = aidw.to_device(inst)
     res = []
-    for speculate in (0, 1):
+    for speculate in (2, 1):
         ctx.set_tuning(0, 0, segments, speculate)
         try:
             res.append(tuple(t.cpu().numpy() for t in ctx.interpolate(
@@ -178,9 +202,9 @@ def test_split_speculation_is_bit_identical(ctx, segments):
     assert np.array_equal(r0, r1) and np.array_equal(a0, a1)
     assert np.array_equal(o0, o1)
     err, a_ref = oracle_check(inst, o0)
-    say("split %d: tiles off alpha_5 %d of %d, err %.3e" % (segments, failing_tiles(a_ref),
-                                                           -(-inst.n // 64), err))
-    assert 0 < failing_tiles(a_ref) < -(-inst.n // 64)
+    fails = failing_tiles(a_ref, tile_order(ctx, inst))
+    say("split %d: tiles off alpha_5 %d of %d, err %.3e" % (segments, fails, -(-inst.n // 64), err))
+    assert 0 < fails < -(-inst.n // 64)
     assert err <= TOL_F32
 
 
