@@ -291,6 +291,18 @@ aidw::ProblemF32 problem_f32(const aidw_problem* p) {
     return q;
 }
 
+// Fewer data points than this: the scans are short, and the order's seven
+// small launches would cost more than tile coherence saves.
+constexpr int64_t kOrderMinPoints = 1024;
+
+int order_bits_for(int mode, int64_t m, int64_t n) {
+    if (mode == 1 || (mode == 0 && m < kOrderMinPoints)) return 0;
+    return aidw::order_bits(n);
+}
+
+int order_passes(int bits) { return (2 * bits + 7) / 8; }
+int order_blocks(int64_t n) { return (int)((n + aidw::kOrderBlock - 1) / aidw::kOrderBlock); }
+
 aidw::ProblemF64 problem_f64(const aidw_problem* p) {
     const int m = (int)p->m, n = (int)p->n;
     const double* xy = static_cast<const double*>(p->data_xy);
@@ -360,22 +372,6 @@ struct F32Plan {
     bool spec;  // the speculative single pass, with pass 2 deferred for failed tiles
     int order_bits;  // Morton bits per axis of the spatial tile order (0: caller's order)
 };
-
-// Fewer data points than this: the scans are short, and the order's seven
-// small launches would cost more than tile coherence saves.
-constexpr int64_t kOrderMinPoints = 1024;
-
-// Morton bits of the spatial tile order of a problem (0: the caller's
-// order).  mode: aidw_tuning.query_order (0 automatic, 1 never, 2 whenever
-// there is more than one tile).  Batched launches and deterministic handles
-// use the automatic choice.
-int order_bits_for(int mode, int64_t m, int64_t n) {
-    if (mode == 1 || (mode == 0 && m < kOrderMinPoints)) return 0;
-    return aidw::order_bits(n);
-}
-
-int order_passes(int bits) { return (2 * bits + 7) / 8; }
-int order_blocks(int64_t n) { return (int)((n + aidw::kOrderBlock - 1) / aidw::kOrderBlock); }
 
 // Order workspace of one problem (plan pl); with L given, laid out at base.
 size_t order_bytes(const F32Plan& pl, int64_t n, aidw::OrderLaunch* L, char* base) {

@@ -79,6 +79,13 @@ aidw_status hip_fail(hipError_t e, const char* what);
 aidw_status validate(const aidw_problem* p);
 AlphaParams alpha_params(const aidw_problem* p);
 ProblemF32 problem_f32(const aidw_problem* p);
+// Morton bits of the spatial tile order of a problem (0: the caller's
+// order).  mode: aidw_tuning.query_order (0 automatic: more than one tile
+// and at least 1024 data points; 1 never; 2 whenever there is more than one
+// tile).  Batched launches, serving and deterministic handles use 0.
+int order_bits_for(int mode, int64_t m, int64_t n);
+int order_passes(int bits);   // 8-bit radix passes for 2 * bits key bits
+int order_blocks(int64_t n);  // sort blocks of n queries
 ProblemF64 problem_f64(const aidw_problem* p);
 aidw_status device_alloc(aidw_t h, size_t bytes, void** out);
 void device_free(aidw_t h, void* p, size_t bytes);

@@ -41,7 +41,9 @@ struct JobRec {
     aidw::SplitPlan sp{};
     int K = 4;
     bool track = false;         // knn_idx wanted: fused items only, index-tracking kernel
-    size_t ws_bytes = 0;        // split workspace, then the two arrival-counter arrays
+    int order_bits = 0;         // spatial tile order (computed at admission), 0: none
+    size_t ws_bytes = 0;        // tile order, split workspace, two arrival-counter arrays
+    size_t split_off = 0;       // offset of the split workspace inside the job's workspace
     size_t counters_off = 0;    // offset of the counters inside the job's workspace
     char* ws = nullptr;         // device address of the job's workspace
     uint64_t zero_seq = 0;      // admin-stream sequence number that cleared its counters
@@ -82,15 +84,30 @@ class HipExecutor : public sv::Executor {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
 
+    // The job's tile order and its split counters are set up on the admin
+    // stream, which every tick carrying the job waits for.
     int admit(uint64_t t, size_t off) override {
         JobRec& r = jobs[t];
-        if (r.sp.segments <= 1) return 0;
+        if (r.ws_bytes == 0) return 0;
         r.ws = arena + off;
-        hipError_t e = hipMemsetAsync(r.ws + r.counters_off, 0,
-                                      2 * sizeof(int) * (size_t)r.sp.tiles, admin);
+        hipError_t e = hipSuccess;
+        if (r.order_bits) {
+            aidw::OrderLaunch L{};
+            const int passes = order_passes(r.order_bits), blocks = order_blocks(r.p.n);
+            aidw::order_workspace_bytes(r.p.n, blocks, 1, passes, &L, r.ws);
+            L.one = aidw::OrderSeg{r.p.qx, r.p.qy, r.p.n, 0, 0, blocks, r.order_bits};
+            L.segments = 1;
+            L.blocks = blocks;
+            L.passes = passes;
+            e = aidw::launch_query_order(L, admin);
+            r.p.order = L.order;
+        }
+        if (e == hipSuccess && r.sp.segments > 1)
+            e = hipMemsetAsync(r.ws + r.counters_off, 0, 2 * sizeof(int) * (size_t)r.sp.tiles,
+                               admin);
         if (e == hipSuccess) e = hipEventRecord(admin_done, admin);
         if (e != hipSuccess) {
-            error = hip_fail(e, "arrival counter clearing");
+            error = hip_fail(e, "job set-up on the admin stream");
             return AIDW_EDEVICE;
         }
         r.zero_seq = ++admin_seq;
@@ -116,7 +133,7 @@ class HipExecutor : public sv::Executor {
             j.p = r.p;
             j.sp = r.sp;
             if (r.sp.segments > 1) {
-                split_workspace_bytes(r.sp, r.p.ap.k, r.p.n, &j.ws, r.ws);
+                split_workspace_bytes(r.sp, r.p.ap.k, r.p.n, &j.ws, r.ws + r.split_off);
                 j.knn_arrivals = reinterpret_cast<int*>(r.ws + r.counters_off);
                 j.sum_arrivals = j.knn_arrivals + r.sp.tiles;
             }
@@ -331,16 +348,31 @@ aidw_status prepare_job(aidw_server* s, const aidw_job* job, JobRec* out, sv::Jo
         spec.cost_scale = kF64CostScale;
     } else {
         r.p = problem_f32(&p);
+        // workspace: tile order | split buffers | arrival counters.  The order
+        // is left out where it would take more than an eighth of the arena.
+        r.order_bits = order_bits_for(0, p.m, p.n);
+        size_t order_bytes = 0;
+        if (r.order_bits) {
+            order_bytes = align_up(aidw::order_workspace_bytes(
+                p.n, order_blocks(p.n), 1, order_passes(r.order_bits), nullptr, nullptr));
+            if (order_bytes > s->ex.arena_bytes / 8) {
+                r.order_bits = 0;
+                order_bytes = 0;
+            }
+        }
+        r.split_off = order_bytes;
+        r.ws_bytes = order_bytes;
         const int64_t seg = (s->opt.segment_points + 31) / 32 * 32;
         if (p.m > seg && p.n > 0 && !r.track) {
             r.sp.seg_len = (int)seg;
             r.sp.segments = (int)((p.m + seg - 1) / seg);
-            r.counters_off = align_up(split_workspace_bytes(r.sp, p.k, p.n, nullptr, nullptr));
+            r.counters_off =
+                r.split_off + align_up(split_workspace_bytes(r.sp, p.k, p.n, nullptr, nullptr));
             r.ws_bytes = r.counters_off + 2 * sizeof(int) * (size_t)r.sp.tiles;
             spec.segments = r.sp.segments;
             spec.seg_len = seg;
-            spec.ws_bytes = r.ws_bytes;
         }
+        spec.ws_bytes = r.ws_bytes;
     }
     r.dataset = job->dataset;
     *out = r;

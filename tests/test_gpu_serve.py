@@ -46,9 +46,10 @@ def ref(inst, idx):
 
 
 def alone(ctx, torch, inst, split):
-    # serving ticks keep the caller's query order: compare with that order
+    # serving orders each job's queries as a single launch does (the
+    # automatic choice), so a fused job's tiles are the same
     data_xy, data_z, query_xy = aidw.to_device(inst)
-    ctx.set_tuning(q_per_lane=1, split_segments=0 if split else 1, query_order=1)
+    ctx.set_tuning(q_per_lane=1, split_segments=0 if split else 1)
     try:
         r = ctx.interpolate(data_xy, data_z, query_xy, inst.k, inst.levels, inst.R_min,
                             inst.R_max, inst.area)
@@ -428,12 +429,8 @@ def test_fp64_and_knn_jobs_through_submit_and_poll(ctx, torch):
             assert np.array_equal(knn.cpu().numpy(), w_knn), inst.name
             assert np.allclose(r_obs.cpu().numpy(), w_robs, rtol=1e-14, atol=0)
         else:
-            ctx.set_tuning(query_order=1)  # serving keeps the caller's order
-            try:
-                got, g_robs, g_al, g_knn = ctx.interpolate(*d, inst.k, inst.levels, inst.R_min,
-                                                           inst.R_max, inst.area, diag=True)
-            finally:
-                ctx.set_tuning()
+            got, g_robs, g_al, g_knn = ctx.interpolate(*d, inst.k, inst.levels, inst.R_min,
+                                                       inst.R_max, inst.area, diag=True)
             assert np.array_equal(out.cpu().numpy(), got.cpu().numpy()), inst.name
             assert np.array_equal(knn.cpu().numpy(), g_knn.cpu().numpy()), inst.name
             assert np.array_equal(r_obs.cpu().numpy(), g_robs.cpu().numpy()), inst.name
