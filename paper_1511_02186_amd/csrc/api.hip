@@ -672,7 +672,8 @@ aidw_status aidw_describe_launch(aidw_t h, const aidw_problem* p, char* buf, siz
     } else {
         const F32Plan pl = plan_f32(h, p);
         if (pl.order_bits)
-            d = "aidw_order_bbox + (aidw_order_hist + aidw_order_scan + aidw_order_scatter) x " +
+            d = "aidw_order_box_part + aidw_order_bbox + (aidw_order_hist + aidw_order_scan + "
+                "aidw_order_scatter) x " +
                 std::to_string(order_passes(pl.order_bits)) + " + ";
         if (pl.spec)
             d += "aidw_abs_max + aidw_f32_fused_spec" + k + "> + aidw_f32_defer_part + "

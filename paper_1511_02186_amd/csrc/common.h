@@ -143,9 +143,10 @@ struct OrderLaunch {
     int blocks;
     int passes;          // ceil(2 * max bits / 8)
     float4* bbox;        // [segments] x0, y0 and cells per unit in x and y
+    float4* part;        // [blocks] each sort block's x0, x1, y0, y1
     unsigned* keys[2];   // [total] keys between passes
     int* vals[2];        // [total] query indices between passes
-    int* hist;           // [256 * blocks] digit counts, then scatter offsets
+    int* hist;           // [blocks][256] digit counts, then scatter offsets
     int* order;          // [total] result: position -> query index in its problem
 };
 

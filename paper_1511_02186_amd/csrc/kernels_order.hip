@@ -44,6 +44,7 @@ size_t order_workspace_bytes(int64_t total, int blocks, int segments, int passes
         return base ? base + o : nullptr;
     };
     char* bbox = take(sizeof(float4) * (size_t)segments);
+    char* part = take(sizeof(float4) * (size_t)blocks);
     char* hist = take(sizeof(int) * 256 * (size_t)blocks);
     char* order = take(sizeof(int) * e);
     char* keys[2] = {nullptr, nullptr};
@@ -54,6 +55,7 @@ size_t order_workspace_bytes(int64_t total, int blocks, int segments, int passes
     }
     if (L && base) {
         L->bbox = reinterpret_cast<float4*>(bbox);
+        L->part = reinterpret_cast<float4*>(part);
         L->hist = reinterpret_cast<int*>(hist);
         L->order = reinterpret_cast<int*>(order);
         for (int i = 0; i < 2; ++i) {
@@ -98,26 +100,34 @@ __device__ __forceinline__ unsigned morton_key(const OrderSeg& s, float4 bb, int
            (spread_bits(cell_of(s.qy[i], bb.y, bb.w, top)) << 1);
 }
 
-// Bounding box of each problem's queries, as (x0, y0, cells / width,
-// cells / height); one workgroup per problem.
-__global__ __launch_bounds__(1024) void aidw_order_bbox(OrderLaunch L) {
-    __shared__ float red[4][1024 / kWaveSize];
-    const OrderSeg s = segment(L, blockIdx.x);
-    float x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
-    for (int i = threadIdx.x; i < s.n; i += blockDim.x) {
-        const float x = s.qx[i], y = s.qy[i];
-        x0 = fminf(x0, x);
-        x1 = fmaxf(x1, x);
-        y0 = fminf(y0, y);
-        y1 = fmaxf(y1, y);
-    }
+// Min and max of x and y over a wave (NaN ignored: fminf/fmaxf keep the
+// other operand).
+__device__ __forceinline__ void wave_box(float& x0, float& x1, float& y0, float& y1) {
     for (int o = kWaveSize / 2; o > 0; o >>= 1) {
         x0 = fminf(x0, __shfl_xor(x0, o));
         x1 = fmaxf(x1, __shfl_xor(x1, o));
         y0 = fminf(y0, __shfl_xor(y0, o));
         y1 = fmaxf(y1, __shfl_xor(y1, o));
     }
-    const int w = threadIdx.x / kWaveSize, waves = blockDim.x / kWaveSize;
+}
+
+// Bounding box of the queries of one sort block, as (x0, x1, y0, y1).
+__global__ __launch_bounds__(kOrderThreads) void aidw_order_box_part(OrderLaunch L) {
+    constexpr int W = kOrderThreads / kWaveSize;
+    __shared__ float red[4][W];
+    const OrderSeg s = segment(L, block_segment(L, blockIdx.x));
+    const int i0 = (blockIdx.x - s.block0) * kOrderBlock;
+    const int i1 = min(s.n, i0 + kOrderBlock);
+    float x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += kOrderThreads) {
+        const float x = s.qx[i], y = s.qy[i];
+        x0 = fminf(x0, x);
+        x1 = fmaxf(x1, x);
+        y0 = fminf(y0, y);
+        y1 = fmaxf(y1, y);
+    }
+    wave_box(x0, x1, y0, y1);
+    const int w = threadIdx.x / kWaveSize;
     if (threadIdx.x % kWaveSize == 0) {
         red[0][w] = x0;
         red[1][w] = x1;
@@ -126,17 +136,36 @@ __global__ __launch_bounds__(1024) void aidw_order_bbox(OrderLaunch L) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int v = 1; v < waves; ++v) {
+        for (int v = 1; v < W; ++v) {
             x0 = fminf(x0, red[0][v]);
             x1 = fmaxf(x1, red[1][v]);
             y0 = fminf(y0, red[2][v]);
             y1 = fmaxf(y1, red[3][v]);
         }
+        L.part[blockIdx.x] = make_float4(x0, x1, y0, y1);
+    }
+}
+
+// Each problem's box from its blocks' boxes, as (x0, y0, cells / width,
+// cells / height); one wave per problem.
+__global__ __launch_bounds__(kWaveSize) void aidw_order_bbox(OrderLaunch L) {
+    const OrderSeg s = segment(L, blockIdx.x);
+    float x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+    for (int b = threadIdx.x; b < s.nblocks; b += kWaveSize) {
+        const float4 v = L.part[s.block0 + b];
+        x0 = fminf(x0, v.x);
+        x1 = fmaxf(x1, v.y);
+        y0 = fminf(y0, v.z);
+        y1 = fmaxf(y1, v.w);
+    }
+    wave_box(x0, x1, y0, y1);
+    if (threadIdx.x == 0) {
         const float cells = (float)(1 << s.bits);
         // zero scale for an empty, single-valued or non-finite extent
         const float sx = x1 > x0 ? __fdiv_rn(cells, x1 - x0) : 0.0f;
         const float sy = y1 > y0 ? __fdiv_rn(cells, y1 - y0) : 0.0f;
-        L.bbox[blockIdx.x] = make_float4(x0, y0, sx < INFINITY ? sx : 0.0f, sy < INFINITY ? sy : 0.0f);
+        L.bbox[blockIdx.x] =
+            make_float4(x0, y0, sx < INFINITY ? sx : 0.0f, sy < INFINITY ? sy : 0.0f);
     }
 }
 
@@ -155,7 +184,7 @@ __device__ __forceinline__ void key_of(const OrderLaunch& L, const OrderSeg& s, 
     }
 }
 
-// Digit counts of one sort block: hist[256 * block0 + digit * nblocks + b].
+// Digit counts of one sort block b: hist[256 * b + digit].
 template <bool FIRST>
 __global__ __launch_bounds__(kOrderThreads) void aidw_order_hist(OrderLaunch L, int shift,
                                                                  const unsigned* keys_in,
@@ -177,7 +206,7 @@ __global__ __launch_bounds__(kOrderThreads) void aidw_order_hist(OrderLaunch L, 
         }
     }
     __syncthreads();
-    L.hist[256 * (int64_t)s.block0 + (int64_t)threadIdx.x * s.nblocks + lb] = h[threadIdx.x];
+    L.hist[256 * (int64_t)blockIdx.x + threadIdx.x] = h[threadIdx.x];
 }
 
 // Counts to scatter offsets, one workgroup per problem: the first position
@@ -187,11 +216,11 @@ __global__ __launch_bounds__(256) void aidw_order_scan(OrderLaunch L) {
     __shared__ int tot[256];
     const OrderSeg s = segment(L, blockIdx.x);
     const int d = threadIdx.x;
-    int* h = L.hist + 256 * (int64_t)s.block0 + (int64_t)d * s.nblocks;
+    int* h = L.hist + 256 * (int64_t)s.block0 + d;  // the problem's blocks are consecutive
     int run = 0;
     for (int b = 0; b < s.nblocks; ++b) {
-        const int v = h[b];
-        h[b] = run;
+        const int v = h[256 * b];
+        h[256 * b] = run;
         run += v;
     }
     tot[d] = run;
@@ -204,7 +233,7 @@ __global__ __launch_bounds__(256) void aidw_order_scan(OrderLaunch L) {
         __syncthreads();
     }
     const int first = s.base + tot[d] - run;
-    for (int b = 0; b < s.nblocks; ++b) h[b] += first;
+    for (int b = 0; b < s.nblocks; ++b) h[256 * b] += first;
 }
 
 // Stable scatter of one sort block.  The block's queries go in chunks of 256
@@ -223,7 +252,7 @@ __global__ __launch_bounds__(kOrderThreads) void aidw_order_scatter(OrderLaunch 
     const OrderSeg s = segment(L, si);
     const int lb = blockIdx.x - s.block0;
     const int t = threadIdx.x, w = t / kWaveSize, lane = t % kWaveSize;
-    offs[t] = L.hist[256 * (int64_t)s.block0 + (int64_t)t * s.nblocks + lb];
+    offs[t] = L.hist[256 * (int64_t)blockIdx.x + t];
     run[t] = 0;
 #pragma unroll
     for (int v = 0; v < W; ++v) wcnt[v][t] = 0;
@@ -271,7 +300,9 @@ __global__ __launch_bounds__(kOrderThreads) void aidw_order_scatter(OrderLaunch 
 
 hipError_t launch_query_order(const OrderLaunch& L, hipStream_t stream) {
     if (L.blocks <= 0 || L.passes <= 0) return hipSuccess;
-    hipLaunchKernelGGL(aidw_order_bbox, dim3((unsigned)L.segments), dim3(1024), 0, stream, L);
+    hipLaunchKernelGGL(aidw_order_box_part, dim3((unsigned)L.blocks), dim3(kOrderThreads), 0,
+                       stream, L);
+    hipLaunchKernelGGL(aidw_order_bbox, dim3((unsigned)L.segments), dim3(kWaveSize), 0, stream, L);
     for (int pass = 0; pass < L.passes; ++pass) {
         const int shift = 8 * pass;
         const bool first = pass == 0, last = pass == L.passes - 1;

@@ -195,7 +195,7 @@ def test_automatic_order_threshold(ctx, torch):
     d = aidw.to_device(inst)
     out = torch.empty(inst.n, device="cuda")
     p = ctx.problem(*d, inst.k, out, inst.levels, inst.R_min, inst.R_max, inst.area)
-    assert aidw.aidw_describe_launch(ctx.h, p).startswith("aidw_order_bbox")
+    assert aidw.aidw_describe_launch(ctx.h, p).startswith("aidw_order_box_part")
     small = workloads.uniform_unit(1000, 300, 3, 8)  # fewer than 1024 points
     ds = aidw.to_device(small)
     ps = ctx.problem(*ds, small.k, out, small.levels, small.R_min, small.R_max, small.area)
