@@ -286,13 +286,17 @@ aidw_status aidw_set_tuning(aidw_t h, const aidw_tuning* t);
 
 /* Autotuner.  Times the candidate launch shapes (queries per lane 1/2/4,
  * no split or the automatic number of data segments, half and twice it,
- * occupancy cap none/4) of an FP32-scaled problem of m data points, n
- * queries and this k on synthetic uniform points, within about budget_s
- * seconds of GPU time, and records the fastest for the size class
- * (floor(log2 m), floor(log2 n), k bucket).  While the handle's tuning is
- * all automatic, later calls in that class use the recorded shape.
- * *best (may be NULL) receives it.  Uses about 12 (m + n) bytes of
- * temporary device memory. */
+ * occupancy cap none/4, and for split launches speculate 0 or 2) of an
+ * FP32-scaled problem of m data points, n queries and this k, on two
+ * synthetic data sets with the same uniform queries: uniform points (alpha
+ * ends at alpha_5 nearly everywhere) and clustered points (16 Gaussians of
+ * widths 1e-4..1e-1 plus 10 % uniform: alpha varies), within about budget_s
+ * seconds of GPU time, and records the shape with the least total time for
+ * the size class (floor(log2 m), floor(log2 n), k bucket).  While the
+ * handle's queries per lane, occupancy cap and split are automatic, later
+ * calls in that class use the recorded shape (a nonzero speculate of the
+ * handle's tuning still wins).  *best (may be NULL) receives it.  Uses
+ * about 24 m + 12 n bytes of temporary device memory. */
 aidw_status aidw_tune(aidw_t h, int64_t m, int64_t n, int k, double budget_s, aidw_tuning* best);
 /* Write the handle's tuning table to `path` as JSON. */
 aidw_status aidw_tune_save(aidw_t h, const char* path);

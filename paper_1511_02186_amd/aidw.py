@@ -274,7 +274,7 @@ def aidw_tune(h, m, n, k, budget_s=10.0):
     t = aidw_tuning()
     check(lib().aidw_tune(h, int(m), int(n), int(k), float(budget_s), ctypes.byref(t)))
     return {"q_per_lane": t.q_per_lane, "max_waves_per_simd": t.max_waves_per_simd,
-            "split_segments": t.split_segments}
+            "split_segments": t.split_segments, "speculate": t.speculate}
 
 
 def aidw_tune_save(h, path) -> int:

@@ -371,6 +371,7 @@ struct F32Plan {
     aidw::SplitPlan sp;
     bool spec;  // the speculative single pass, with pass 2 deferred for failed tiles
     int order_bits;  // Morton bits per axis of the spatial tile order (0: caller's order)
+    bool split_spec = false;  // speculative sums per data segment in the split kernels
 };
 
 // Order workspace of one problem (plan pl); with L given, laid out at base.
@@ -384,16 +385,6 @@ size_t order_bytes(const F32Plan& pl, int64_t n, aidw::OrderLaunch* L, char* bas
 // unless the handle is deterministic or its tuning turns them off.
 bool speculation_allowed(const aidw_ctx* h) { return !h->deterministic && h->tuning.speculate != 1; }
 
-// Speculative sums inside the split kernels only when the tuning asks for
-// them (speculate = 2).  There a tile that keeps them saves little over the
-// one-transcendental pass 2 it replaces (the distances, about 8 % of that
-// pass measured on uniform data), while a tile that forms them and then
-// misses alpha_5 pays a second pass 1; each segment decides from 1/32 of
-// its own points, so on clustered data many tiles do (m = n = 2^18
-// clustered: 25.9 ms with them, 21.7 ms without; uniform: 18.5 against
-// 19.8 ms).
-bool split_speculation(const aidw_ctx* h) { return speculation_allowed(h) && h->tuning.speculate == 2; }
-
 // Waves in one round of the device (8 per SIMD, 4 SIMDs per CU): what the
 // deferred pass 2 of the speculative launch aims to fill.
 int round_waves(const aidw_ctx* h) { return (h->cu_count > 0 ? h->cu_count : 256) * 4 * 8; }
@@ -404,8 +395,11 @@ F32Plan plan_f32(const aidw_ctx* h, const aidw_problem* p) {
     if (h->deterministic)
         t = aidw_tuning{1, 0, 1};  // the unsplit one-query-per-lane kernel
     else if (!t.q_per_lane && !t.max_waves_per_simd && !t.split_segments &&
-             tuned_shape(h, p->m, p->n, p->k, &tuned))
+             tuned_shape(h, p->m, p->n, p->k, &tuned)) {
+        if (t.speculate == 0) t.speculate = tuned.speculate;  // else the handle's choice
+        tuned.speculate = t.speculate;
         t = tuned;
+    }
     F32Plan pl{aidw::LaunchF32{t.q_per_lane ? t.q_per_lane : default_q_per_lane(h, p->n),
                                t.max_waves_per_simd},
                aidw::SplitPlan{1, (int)p->m, 0}, false,
@@ -418,6 +412,16 @@ F32Plan plan_f32(const aidw_ctx* h, const aidw_problem* p) {
     pl.spec = !h->deterministic && !p->knn_idx && pl.cfg.q_per_lane == 1 &&
               pl.cfg.max_waves_per_simd == 0 && pl.sp.segments == 1 &&
               speculation_allowed(h) && problem_f32(p).spec_power != 0;
+    // Speculative sums inside the split kernels only when the tuning (the
+    // handle's, else the autotuner's shape for the size class) asks for them
+    // (speculate = 2).  There a tile that keeps them saves little over the
+    // one-transcendental pass 2 it replaces (the distances, about 8 % of that
+    // pass measured on uniform data), while a tile that forms them and then
+    // misses alpha_5 pays a second pass 1; each segment decides from 1/32 of
+    // its own points, so on clustered data many tiles do (m = n = 2^18
+    // clustered: 25.9 ms with them, 21.7 ms without; uniform: 18.5 against
+    // 19.8 ms).
+    pl.split_spec = speculation_allowed(h) && t.speculate == 2;
     return pl;
 }
 
@@ -460,7 +464,7 @@ hipError_t launch_f32(aidw_t h, const aidw_problem* p, const F32Plan& pl, char* 
         if (e == hipSuccess) e = aidw::launch_aidw_f32_spec(q, dw, h->stream);
         return e;
     }
-    if (!split_speculation(h)) q.spec_power = 0;  // the split kernels speculate when it is set
+    if (!pl.split_spec) q.spec_power = 0;  // the split kernels speculate when it is set
     aidw::SplitWorkspace ws{};
     if (pl.sp.segments > 1) split_workspace_bytes(pl.sp, p->k, p->n, &ws, rest);
     e = aidw::launch_abs_max(q.dz, q.m, zmax, h->stream);

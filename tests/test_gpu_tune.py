@@ -25,6 +25,8 @@ def test_tune_save_load_and_use(torch, tmp_path):
     try:
         best = aidw.aidw_tune(ctx.h, 20000, 300, 10, budget_s=2.0)
         assert best["q_per_lane"] in (1, 2, 4) and best["split_segments"] >= 1
+        assert best["speculate"] in (0, 2)
+        assert best["speculate"] == 0 or best["split_segments"] > 1
         path = tmp_path / "tune.json"
         aidw.check(aidw.aidw_tune_save(ctx.h, path))
         table = json.loads(path.read_text())
@@ -53,6 +55,22 @@ def test_tune_save_load_and_use(torch, tmp_path):
         other = tmp_path / "other.json"
         other.write_text("{}\n")
         assert aidw.aidw_tune_load(ctx2.h, other) == aidw.AIDW_EINVAL
+        bad_spec = tmp_path / "bad_spec.json"
+        bad_spec.write_text('{"format": "libaidw-tuning-1", "entries": [\n'
+                            '  {"m_log2": 3, "n_log2": 3, "K": 10, "q_per_lane": 1, '
+                            '"max_waves_per_simd": 0, "split_segments": 4, "speculate": 1, '
+                            '"ms": 1.0}\n]}\n')
+        assert aidw.aidw_tune_load(ctx2.h, bad_spec) == aidw.AIDW_EINVAL
+        # an entry written without the speculate field still loads (as 0)
+        old = tmp_path / "old.json"
+        old.write_text('{"format": "libaidw-tuning-1", "entries": [\n'
+                       '  {"m_log2": 3, "n_log2": 3, "K": 10, "q_per_lane": 1, '
+                       '"max_waves_per_simd": 0, "split_segments": 1, "ms": 1.0}\n]}\n')
+        aidw.check(aidw.aidw_tune_load(ctx2.h, old))
+        again = tmp_path / "old_again.json"
+        aidw.check(aidw.aidw_tune_save(ctx2.h, again))
+        assert json.loads(again.read_text())["entries"][0]["speculate"] == 0
+        aidw.check(aidw.aidw_tune_load(ctx2.h, path))
     finally:
         ctx2.close()
     # the same table through aidw_options.tune_path at creation
@@ -78,3 +96,33 @@ def test_tune_rejects_bad_sizes(torch):
             assert ei.value.status == aidw.AIDW_EINVAL
     finally:
         ctx.close()
+
+
+def test_tuned_split_speculation_is_used(torch, tmp_path):
+    # a tuned entry may ask for the speculative sums in the split kernels;
+    # calls of that size class then run them (the result is bit-identical to
+    # the split without them) and stay within the bar
+    inst = workloads.paper_scale(m=20000, n=300, seed=9, k=10)
+    d = aidw.to_device(inst)
+    outs = []
+    for spec in (2, 0):
+        path = tmp_path / ("t%d.json" % spec)
+        path.write_text('{"format": "libaidw-tuning-1", "entries": [\n'
+                        '  {"m_log2": 14, "n_log2": 8, "K": 10, "q_per_lane": 1, '
+                        '"max_waves_per_simd": 0, "split_segments": 4, "speculate": %d, '
+                        '"ms": 1.0}\n]}\n' % spec)
+        ctx = aidw.Context(0, tune_path=path)
+        try:
+            out = torch.empty(inst.n, device="cuda")
+            p = ctx.problem(*d, inst.k, out, inst.levels, inst.R_min, inst.R_max, inst.area)
+            assert "4 data segments" in aidw.aidw_describe_launch(ctx.h, p)
+            outs.append(ctx.interpolate(*d, inst.k, inst.levels, inst.R_min, inst.R_max,
+                                        inst.area).cpu().numpy())
+        finally:
+            ctx.close()
+    assert np.array_equal(outs[0], outs[1])
+    want = oracle.run(inst.data_x, inst.data_y, inst.data_z, inst.query_x, inst.query_y, inst.k,
+                      area=inst.area)
+    scale = oracle.run(inst.data_x, inst.data_y, np.abs(inst.data_z), inst.query_x,
+                       inst.query_y, inst.k, area=inst.area)
+    assert np.max(np.abs(outs[0] - want) / scale) <= 1e-4
