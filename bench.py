@@ -84,8 +84,8 @@ def parse():
                     help="skip timing pass 1 through the uniform grid (AIDW_FLAG_GRID_KNN)")
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the issue-cost probe (SIMD cycles of an FP32 FMA and an exp2)")
-    ap.add_argument("--serve-requests", type=int, default=1000,
-                    help="requests of the 2000 req/s Poisson serving run")
+    ap.add_argument("--serve-requests", type=int, default=10000,
+                    help="requests of the 2000 req/s Poisson serving run (5 s of arrivals)")
     ap.add_argument("--serve-sweep-requests", type=int, default=200,
                     help="requests of each lower-rate serving run (250, 500, 1000 req/s)")
     ap.add_argument("--ablation", action="store_true",
@@ -96,7 +96,7 @@ def parse():
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the plain FP64 small workload, the clustered workload and "
                          "standard IDW")
-    ap.add_argument("--check", type=int, default=64,
+    ap.add_argument("--check", type=int, default=256,
                     help="queries checked against the oracle after timing (0 = none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy, the reference for HBM counters")
