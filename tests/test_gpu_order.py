@@ -208,3 +208,26 @@ def test_automatic_order_threshold(ctx, torch):
         assert "aidw_order" not in aidw.aidw_describe_launch(ctx.h, p)
     finally:
         ctx.set_tuning()
+
+
+def test_order_with_non_finite_queries(ctx, torch):
+    # NaN and infinite coordinates land in edge cells: the order stays a
+    # permutation, and an ordered launch still gives every finite query the
+    # oracle's result (the others come out NaN, as in the caller's order)
+    inst = workloads.uniform_unit(5000, 700, 46, 10)
+    qx, qy = inst.query_x.copy(), inst.query_y.copy()
+    bad = np.arange(0, 700, 37)
+    qx[bad[::3]] = np.nan
+    qy[bad[1::3]] = np.inf
+    qx[bad[2::3]] = -np.inf
+    order = device_order(ctx, torch, qx, qy)
+    assert np.array_equal(np.sort(order), np.arange(qx.size))
+    inst.query_x, inst.query_y = qx, qy
+    o1, r1, a1, _ = _run(ctx, torch, inst, 2)
+    o0, r0, a0, _ = _run(ctx, torch, inst, 1)
+    good = np.setdiff1d(np.arange(inst.n), bad)
+    assert np.array_equal(r0[good], r1[good]) and np.array_equal(a0[good], a1[good])
+    assert np.allclose(o1[good], o0[good], rtol=1e-5, atol=1e-6 * np.abs(o0[good]).max())
+    assert np.array_equal(np.isnan(o1), np.isnan(o0))
+    err = _oracle_err(inst, o1, good[::20])
+    assert err <= TOL_F32
