@@ -255,7 +255,8 @@ typedef struct aidw_tuning {
     int split_segments;      /* split the m data points into this many segments
                                 processed in parallel (1: never split); chosen
                                 automatically when the 64-query tiles give fewer
-                                than two rounds of 8 waves per SIMD */
+                                than two rounds of 8 waves per SIMD (1.5 rounds
+                                when the speculative single pass applies) */
     int speculate;           /* 0: when alpha_5 is a whole power in [1, 8], pass 1
                                 of the unsplit launch also forms the pass-2 sums of
                                 that power, which stand for every 64-query tile

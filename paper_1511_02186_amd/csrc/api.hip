@@ -409,9 +409,18 @@ F32Plan plan_f32(const aidw_ctx* h, const aidw_problem* p) {
     // kernel when alpha_5 is a whole power (a split problem speculates per
     // segment, inside the split kernels); it is off in deterministic mode,
     // which promises the kernel batched launches use.
-    pl.spec = !h->deterministic && !p->knn_idx && pl.cfg.q_per_lane == 1 &&
-              pl.cfg.max_waves_per_simd == 0 && pl.sp.segments == 1 &&
-              speculation_allowed(h) && problem_f32(p).spec_power != 0;
+    const bool spec_ok = !h->deterministic && !p->knn_idx && pl.cfg.q_per_lane == 1 &&
+                         pl.cfg.max_waves_per_simd == 0 && speculation_allowed(h) &&
+                         problem_f32(p).spec_power != 0;
+    // The single pass holds the unsplit launch down to 1.5 rounds of tiles
+    // (two for the two-pass kernel).  Measured, unsplit against the
+    // automatic split, uniform + clustered data of m = n: 1.95 rounds 545
+    // against 577 ms, 1.5 rounds 338 against 348, 1.2 rounds 228 against
+    // 224, 0.95 rounds 147 against 141.
+    if (spec_ok && t.split_segments == 0 && pl.sp.segments > 1 &&
+        2 * (int64_t)pl.sp.tiles >= 3 * (int64_t)round_waves(h))
+        pl.sp = aidw::SplitPlan{1, (int)p->m, pl.sp.tiles};
+    pl.spec = spec_ok && pl.sp.segments == 1;
     // Speculative sums inside the split kernels only when the tuning (the
     // handle's, else the autotuner's shape for the size class) asks for them
     // (speculate = 2).  There a tile that keeps them saves little over the

@@ -226,19 +226,26 @@ def _plan(ctx, torch, inst, n, levels):
     return aidw.aidw_describe_launch(ctx.h, p)
 
 
-def test_automatic_split_boundaries(ctx, torch):
-    """The automatic plan splits m below two rounds of 64-query tiles (8
-    waves per SIMD): the unsplit launch is the speculative single pass when
-    alpha_5 is whole and the two-pass kernel otherwise; the split kernels
-    speculate per segment."""
+def split_boundary(torch, levels):
+    """Queries at which the automatic plan stops splitting m: 1.5 rounds of
+    64-query tiles (8 waves per SIMD) when alpha_5 is whole (the speculative
+    single pass), two rounds otherwise (the two-pass kernel)."""
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     rnd = cus * 4 * 8 * 64  # queries in one round of tiles
-    inst = workloads.paper_scale(m=1 << 14, n=2 * rnd, seed=78, k=15)
+    return 3 * rnd // 2 if levels[4] == int(levels[4]) else 2 * rnd
+
+
+def test_automatic_split_boundaries(ctx, torch):
+    """Above the boundary the unsplit launch is the speculative single pass
+    when alpha_5 is whole and the two-pass kernel otherwise; below it the
+    split kernels run."""
     whole5, frac5 = (1, 2, 3, 4, 5), (1, 2, 3, 4, 4.5)
-    assert "aidw_f32_fused_spec<16>" in _plan(ctx, torch, inst, 2 * rnd, whole5)
-    assert "aidw_f32_knn_part<16>" in _plan(ctx, torch, inst, 2 * rnd - 64, whole5)
-    assert "aidw_f32_fused<16, 1, false>" in _plan(ctx, torch, inst, 2 * rnd, frac5)
-    assert "aidw_f32_knn_part<16>" in _plan(ctx, torch, inst, 2 * rnd - 64, frac5)
+    nw, nf = split_boundary(torch, whole5), split_boundary(torch, frac5)
+    inst = workloads.paper_scale(m=1 << 14, n=max(nw, nf), seed=78, k=15)
+    assert "aidw_f32_fused_spec<16>" in _plan(ctx, torch, inst, nw, whole5)
+    assert "aidw_f32_knn_part<16>" in _plan(ctx, torch, inst, nw - 64, whole5)
+    assert "aidw_f32_fused<16, 1, false>" in _plan(ctx, torch, inst, nf, frac5)
+    assert "aidw_f32_knn_part<16>" in _plan(ctx, torch, inst, nf - 64, frac5)
 
 
 @pytest.mark.parametrize("levels", [(1, 2, 3, 4, 5), (1, 2, 3, 4, 4.5)])
@@ -248,9 +255,7 @@ def test_automatic_split_boundary(ctx, torch, levels):
     both within the bar on sampled queries."""
     import copy
 
-    cus = torch.cuda.get_device_properties(0).multi_processor_count
-    rnd = cus * 4 * 8 * 64
-    n = 2 * rnd
+    n = split_boundary(torch, levels)
     inst = workloads.paper_scale(m=1 << 16, n=n, seed=77, k=15)
     inst.levels = levels
     below = copy.copy(inst)
