@@ -196,9 +196,14 @@ namespace detail {
 // SIMD.  Below that the fused kernel leaves SIMDs short of waves to pair
 // instructions from (one round or less: 102 ms fused against 81 ms in 8
 // segments at m = 2^20, n = 2^18), so the problem runs as (tile, segment)
-// waves, about four rounds' worth, with segments of at least kMinSegment
+// waves, about eight rounds' worth, with segments of at least kMinSegment
 // points.  At two rounds the two are even (m = n = 2^20: 306 ms fused,
 // 300-306 ms in 2-8 segments), and the fused kernel needs no workspace.
+// Eight rounds rather than four: tiles differ in cost (the one- or the
+// two-transcendental pass 2), and smaller items even out the last round
+// (in spatial tile order, 8 against 16 segments: clustered m = n = 2^18
+// 21.4 / 20.9 ms, m = 2^20, n = 2^18 76.8 / 74.2 ms, the same clustered
+// 83.8 / 80.9 ms; 32 segments gain under 1 % more).
 constexpr int kMinSegment = 2048;
 
 aidw::SplitPlan split_plan_for(const aidw_ctx* h, const aidw_tuning& t, int64_t m, int64_t n) {
@@ -207,7 +212,7 @@ aidw::SplitPlan split_plan_for(const aidw_ctx* h, const aidw_tuning& t, int64_t 
     if (want == 0) {
         const int64_t round = (int64_t)(h->cu_count > 0 ? h->cu_count : 256) * 4 * 8;
         if (sp.tiles >= 2 * round) return sp;
-        want = (int)std::min<int64_t>((4 * round + sp.tiles - 1) / sp.tiles, 1 << 20);
+        want = (int)std::min<int64_t>((8 * round + sp.tiles - 1) / sp.tiles, 1 << 20);
     }
     int64_t seg = (m + want - 1) / want;
     if (t.split_segments == 0) seg = std::max<int64_t>(seg, kMinSegment);

@@ -95,7 +95,7 @@ def test_noalloc_fp64_equals_interpolate_ex(ctx, torch):
 
 
 def test_noalloc_fits_a_larger_split_into_the_scratch(ctx, torch):
-    # m = 2^20, n = 2^16: the automatic plan (32 segments, about 130 MB)
+    # m = 2^20, n = 2^16: the automatic plan (64 segments, about 320 MB)
     # exceeds the scratch, so the call runs in fewer segments
     inst = workloads.paper_scale(m=1 << 20, n=1 << 16, seed=13, k=15)
     say("noalloc with a reduced split: m=2^20 n=2^16 k=15")
