@@ -193,7 +193,8 @@ namespace detail {
 
 // Number of data segments for an FP32-scaled problem.  1 (the fused kernel)
 // when the 64-query tiles alone give at least two rounds of 8 waves per
-// SIMD.  Below that the fused kernel leaves SIMDs short of waves to pair
+// SIMD (plan_f32 lowers that to 1.5 rounds for the speculative single
+// pass).  Below that the fused kernel leaves SIMDs short of waves to pair
 // instructions from (one round or less: 102 ms fused against 81 ms in 8
 // segments at m = 2^20, n = 2^18), so the problem runs as (tile, segment)
 // waves, about eight rounds' worth, with segments of at least kMinSegment
