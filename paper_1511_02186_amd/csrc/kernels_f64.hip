@@ -5,9 +5,14 @@
 //    so they are bit-identical to a plain C evaluation; the k nearest are
 //    kept in a register list ordered by (d^2, data index) (Sec. 3.1.2);
 //  * alpha from Eq. 2-6;
-//  * pass 2: w = d^-alpha evaluated as pow(d^2, -alpha/2), unscaled, with
-//    both sums of Eq. 1 Neumaier-compensated.  A query that coincides with
-//    data points (d = 0, alpha > 0) returns the mean z of those points.
+//  * pass 2: w = d^-alpha, unscaled, with both sums of Eq. 1
+//    Neumaier-compensated: in a wave whose 64 queries share one whole alpha A
+//    in [1, 8] (alpha_5 of the paper's levels, most tiles of uniform data)
+//    as 1 / (d2^(A div 2) sqrt(d2)^(A mod 2)) with IEEE-rounded products,
+//    square root and division, within a few ulp of pow; otherwise
+//    pow(d^2, -alpha/2) (a per-lane choice would run both in mixed waves).
+//    A query that coincides with data points (d = 0, alpha > 0) returns the
+//    mean z of those points.
 //
 // Data points are wave-uniform and are read with scalar loads, as in the
 // FP32-scaled kernel.  This kernel is the precision reference and the
@@ -38,6 +43,36 @@ struct Neumaier {
     }
     __device__ __forceinline__ double value() const { return s + c; }
 };
+
+// A whole alpha in [1, 8], else 0.
+__device__ __forceinline__ int whole_alpha(double al) {
+    return (al >= 1.0 && al <= 8.0 && al == floor(al)) ? (int)al : 0;
+}
+
+// d^-A from d^2 for a whole A in [1, 8]: d2 multiplied in A div 2 times,
+// times sqrt(d2) for odd A, then one division (about A/2 + 2 roundings in
+// all, against pow's one; FP64 keeps that far below the 1e-12 bar).
+template <int A>
+__device__ __forceinline__ double whole_weight(double d2) {
+    double q = 1.0;
+#pragma unroll
+    for (int i = 0; i < A / 2; ++i) q *= d2;
+    if constexpr (A % 2 == 1) q *= sqrt(d2);
+    return 1.0 / q;
+}
+
+// The same for a run-time A, operation for operation (a multiply by 1.0 is
+// exact), for kernels that cannot dispatch on A.
+__device__ __forceinline__ double whole_weight_rt(double d2, int A) {
+    const int h = A >> 1;
+    double q = 1.0;
+    q = h >= 1 ? q * d2 : q;
+    q = h >= 2 ? q * d2 : q;
+    q = h >= 3 ? q * d2 : q;
+    q = h >= 4 ? q * d2 : q;
+    q *= (A & 1) ? sqrt(d2) : 1.0;
+    return 1.0 / q;
+}
 
 // Data are read through the constant address space: at wave-uniform
 // addresses such loads are scalar, also when the problem itself was loaded
@@ -106,14 +141,37 @@ __device__ __forceinline__ void f64_query(const ProblemF64& p, int qi) {
     const double d2min = list_min<K, double>(top, p.ap.k);
     const bool coincident = (d2min == 0.0) && (al > 0.0);
     const double e = -0.5 * al;
+    const int A = coincident ? 0 : whole_alpha(al);
 
     // ---- pass 2 (Eq. 1) -----------------------------------------------------
     Neumaier num, den;
-    for (j = 0; j < m; ++j) {
-        const double d2 = sqdist64(qx, qy, X[j], Y[j]);
-        const double w = coincident ? (d2 == 0.0 ? 1.0 : 0.0) : pow(d2, e);
-        num.add(w * Z[j]);
-        den.add(w);
+    const int a0 = __builtin_amdgcn_readfirstlane(A);
+    bool done = false;
+    if (a0 != 0 && __all(A == a0)) {  // one whole power in every lane
+        auto scan = [&](auto weight) {
+            for (int jj = 0; jj < m; ++jj) {
+                const double w = weight(sqdist64(qx, qy, X[jj], Y[jj]));
+                num.add(w * Z[jj]);
+                den.add(w);
+            }
+        };
+        done = true;
+        switch (a0) {
+#define AIDW_F64_WHOLE(AA) \
+    case AA: scan([](double d2) { return whole_weight<AA>(d2); }); break;
+            AIDW_F64_WHOLE(1) AIDW_F64_WHOLE(2) AIDW_F64_WHOLE(3) AIDW_F64_WHOLE(4)
+            AIDW_F64_WHOLE(5) AIDW_F64_WHOLE(6) AIDW_F64_WHOLE(7) AIDW_F64_WHOLE(8)
+#undef AIDW_F64_WHOLE
+            default: done = false; break;
+        }
+    }
+    if (!done) {
+        for (j = 0; j < m; ++j) {
+            const double d2 = sqdist64(qx, qy, X[j], Y[j]);
+            const double w = coincident ? (d2 == 0.0 ? 1.0 : 0.0) : pow(d2, e);
+            num.add(w * Z[j]);
+            den.add(w);
+        }
     }
 
     if (qi < p.n) {
@@ -248,10 +306,15 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f64_variant(ProblemF64 p,
     const double d2min = list_min<K, double>(top, p.ap.k);
     const bool coincident = (d2min == 0.0) && (al > 0.0);
     const double e = -0.5 * al;
+    const int A = coincident ? 0 : whole_alpha(al);
+    // the plain kernel's choice, made per wave of 64 consecutive queries
+    const int a0 = __builtin_amdgcn_readfirstlane(A);
+    const bool whole = a0 != 0 && __all(A == a0);
     Neumaier num, den;
     walk([&](const D4& pt, int) {
         const double d2 = sqdist64(qx, qy, pt.x, pt.y);
-        const double w = coincident ? (d2 == 0.0 ? 1.0 : 0.0) : pow(d2, e);
+        const double w = coincident ? (d2 == 0.0 ? 1.0 : 0.0)
+                                    : (whole ? whole_weight_rt(d2, a0) : pow(d2, e));
         num.add(w * pt.z);
         den.add(w);
     });
