@@ -277,7 +277,9 @@ typedef struct aidw_tuning {
                                 tile.  Each query's result is its own in every
                                 order; the grouping only sets which pass-2 loop a
                                 wave takes, so results agree to rounding.  Batched
-                                launches and deterministic handles use 0. */
+                                launches and deterministic handles use 0.  The
+                                order needs about 20 n bytes of workspace; a call
+                                whose HBM budget cannot hold it runs without. */
 } aidw_tuning;
 
 /* Fix the launch shape used for FP32-scaled problems (NULL restores the

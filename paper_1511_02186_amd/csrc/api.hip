@@ -510,8 +510,13 @@ aidw_status run_problem(aidw_t h, const aidw_problem* p) {
         e = run_grid(h, p, &gst);
         if (gst != AIDW_OK) return gst;
     } else if (p->precision == AIDW_FP32_SCALED) {
-        const F32Plan pl = plan_f32(h, p);
+        F32Plan pl = plan_f32(h, p);
         st = ensure_workspace(h, f32_workspace_bytes(h, pl, p));
+        if (st == AIDW_ENOMEM && pl.order_bits) {
+            // the tile order only sets the speed: without its ~20 n bytes
+            pl.order_bits = 0;
+            st = ensure_workspace(h, f32_workspace_bytes(h, pl, p));
+        }
         if (st != AIDW_OK) return st;
         e = launch_f32(h, p, pl, static_cast<char*>(h->workspace));
     } else {

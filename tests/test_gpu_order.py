@@ -231,3 +231,23 @@ def test_order_with_non_finite_queries(ctx, torch):
     assert np.array_equal(np.isnan(o1), np.isnan(o0))
     err = _oracle_err(inst, o1, good[::20])
     assert err <= TOL_F32
+
+
+def test_order_left_out_under_a_tight_budget(torch):
+    # two rounds of tiles and a non-whole alpha_5: the unsplit two-pass kernel,
+    # whose workspace is a few bytes; the order's ~20 n bytes do not fit a
+    # 4 MiB budget, so the call runs in the caller's order instead of failing
+    inst = workloads.paper_scale(m=2048, n=(1 << 20) + 64, seed=47, k=10)
+    inst.levels = (1, 2, 3, 4, 4.5)
+    d = aidw.to_device(inst)
+    tight = aidw.Context(0, hbm_budget_bytes=4 << 20)
+    plain = aidw.Context(0)
+    try:
+        out = tight.interpolate(*d, inst.k, inst.levels, inst.R_min, inst.R_max, inst.area)
+        plain.set_tuning(query_order=1)
+        ref_out = plain.interpolate(*d, inst.k, inst.levels, inst.R_min, inst.R_max, inst.area)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref_out.cpu().numpy())
+    finally:
+        tight.close()
+        plain.close()
