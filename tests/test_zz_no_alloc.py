@@ -132,3 +132,24 @@ def test_noalloc_rejects_grid_mode(ctx, torch):
     p = ctx.problem(data_xy, data_z, query_xy, inst.k, out, area=inst.area,
                     flags=aidw.AIDW_FLAG_GRID_KNN)
     assert aidw.aidw_interpolate_noalloc(ctx.h, p) == aidw.AIDW_EINVAL
+
+
+def test_noalloc_drops_the_order_beyond_the_scratch(ctx, torch):
+    # 2^22 queries: the tile order alone (about 20 n bytes) would leave the
+    # 64 MiB scratch no room, so the allocation-free call runs the queries in
+    # the caller's order (and without the speculative pass's workspace where
+    # that does not fit either); every query is written, the outputs agree
+    # with aidw_interpolate_ex (which orders them) to rounding, and sampled
+    # queries with the oracle
+    inst = workloads.uniform_unit(4096, 1 << 22, seed=16, k=10)
+    say("noalloc beyond the order's scratch: m=4096 n=2^22 k=10")
+    st_a, out_a = _run(ctx, torch, inst, "noalloc")
+    assert st_a == aidw.AIDW_OK, aidw.last_error(ctx.h)
+    st_b, out_b = _run(ctx, torch, inst, "ex")
+    assert st_b == aidw.AIDW_OK, aidw.last_error(ctx.h)
+    assert not np.isnan(out_a).any()
+    assert np.allclose(out_a, out_b, rtol=1e-5, atol=1e-6 * np.abs(out_b).max())
+    idx = np.linspace(0, inst.n - 1, 48).astype(np.int64)
+    err = _oracle_err(inst, out_a, idx)
+    say("  max rel err vs oracle on %d queries: %.3e" % (idx.size, err))
+    assert err <= TOL_F32
