@@ -274,7 +274,11 @@ typedef struct aidw_tuning {
                                 alpha), when there is more than one tile and at
                                 least 1024 data points; 1: the caller's order;
                                 2: Morton order whenever there is more than one
-                                tile.  Each query's result is its own in every
+                                tile.  Unless 1, a split problem's pass 2 (alpha is
+                                then known for every query) also regroups its
+                                waves by the loop they take (whole power or not),
+                                as long as no speculative sums are formed.  Each
+                                query's result is its own in every
                                 order; the grouping only sets which pass-2 loop a
                                 wave takes, so results agree to rounding.  Batched
                                 launches and deterministic handles use 0.  The

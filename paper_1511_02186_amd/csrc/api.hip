@@ -246,7 +246,7 @@ aidw::SplitPlan grid_pass2_plan(const aidw_ctx* h, const aidw_tuning& t, int64_t
 }
 
 size_t split_workspace_bytes(const aidw::SplitPlan& sp, int k, int64_t n, aidw::SplitWorkspace* ws,
-                             char* base) {
+                             char* base, bool regroup) {
     const int64_t tiles = (n + aidw::kWaveSize - 1) / aidw::kWaveSize;
     const size_t part = (size_t)sp.segments * k * n * sizeof(float);
     const size_t qpar = 4 * (size_t)n * sizeof(float);
@@ -258,14 +258,23 @@ size_t split_workspace_bytes(const aidw::SplitPlan& sp, int k, int64_t n, aidw::
     const size_t o_psum = up(o_qpar + qpar);
     const size_t o_seg = up(o_psum + psum);
     const size_t o_tile = up(o_seg + seg_ok);
+    const size_t end_tile = o_tile + tiles * sizeof(int);
+    // pass-2 regrouping: keys, sort histogram, the regrouped order
+    const size_t blocks = (size_t)((n + aidw::kOrderBlock - 1) / aidw::kOrderBlock);
+    const size_t o_key = up(end_tile);
+    const size_t o_hist = up(o_key + sizeof(unsigned) * (size_t)n);
+    const size_t o_ord = up(o_hist + sizeof(int) * 256 * blocks);
     if (ws) {
         ws->part = reinterpret_cast<float*>(base);
         ws->qpar = reinterpret_cast<float*>(base + o_qpar);
         ws->psum = reinterpret_cast<double*>(base + o_psum);
         ws->seg_ok = reinterpret_cast<int*>(base + o_seg);
         ws->tile_ok = reinterpret_cast<int*>(base + o_tile);
+        ws->p2key = regroup ? reinterpret_cast<unsigned*>(base + o_key) : nullptr;
+        ws->p2hist = regroup ? reinterpret_cast<int*>(base + o_hist) : nullptr;
+        ws->p2order = regroup ? reinterpret_cast<int*>(base + o_ord) : nullptr;
     }
-    return o_tile + tiles * sizeof(int);
+    return regroup ? o_ord + sizeof(int) * (size_t)n : end_tile;
 }
 
 // Problems of fewer data points than this keep the two passes: the single
@@ -378,6 +387,7 @@ struct F32Plan {
     bool spec;  // the speculative single pass, with pass 2 deferred for failed tiles
     int order_bits;  // Morton bits per axis of the spatial tile order (0: caller's order)
     bool split_spec = false;  // speculative sums per data segment in the split kernels
+    bool regroup = false;     // split pass 2 in waves regrouped by their loop
 };
 
 // Order workspace of one problem (plan pl); with L given, laid out at base.
@@ -437,6 +447,11 @@ F32Plan plan_f32(const aidw_ctx* h, const aidw_problem* p) {
     // clustered: 25.9 ms with them, 21.7 ms without; uniform: 18.5 against
     // 19.8 ms).
     pl.split_spec = speculation_allowed(h) && t.speculate == 2;
+    // Split pass 2 runs after alpha is known everywhere: its waves can take
+    // the positions regrouped by the loop they need (the caller's order, 1,
+    // keeps the pass-1 tiles).
+    pl.regroup = pl.sp.segments > 1 && !pl.split_spec &&
+                 (h->deterministic ? 0 : h->tuning.query_order) != 1;
     return pl;
 }
 
@@ -446,7 +461,9 @@ size_t f32_workspace_bytes(const aidw_ctx* h, const F32Plan& pl, const aidw_prob
     const size_t head = kZmaxSlot + order_bytes(pl, p->n, nullptr, nullptr);
     if (pl.spec) return head + aidw::spec_workspace_bytes(p->n, round_waves(h), nullptr, nullptr);
     return head +
-           (pl.sp.segments > 1 ? split_workspace_bytes(pl.sp, p->k, p->n, nullptr, nullptr) : 0);
+           (pl.sp.segments > 1 ? split_workspace_bytes(pl.sp, p->k, p->n, nullptr, nullptr,
+                                                       pl.regroup)
+                               : 0);
 }
 
 // Queue the tile-order kernels of plan pl (order workspace at base) and
@@ -481,7 +498,7 @@ hipError_t launch_f32(aidw_t h, const aidw_problem* p, const F32Plan& pl, char* 
     }
     if (!pl.split_spec) q.spec_power = 0;  // the split kernels speculate when it is set
     aidw::SplitWorkspace ws{};
-    if (pl.sp.segments > 1) split_workspace_bytes(pl.sp, p->k, p->n, &ws, rest);
+    if (pl.sp.segments > 1) split_workspace_bytes(pl.sp, p->k, p->n, &ws, rest, pl.regroup);
     e = aidw::launch_abs_max(q.dz, q.m, zmax, h->stream);
     if (e == hipSuccess) e = aidw::launch_aidw_f32(q, pl.cfg, &pl.sp, &ws, h->stream);
     return e;
@@ -762,6 +779,7 @@ aidw_status aidw_interpolate_noalloc(aidw_t h, const aidw_problem* p) {
             pl.order_bits = 0;
         const size_t cap_rest = cap - order_bytes(pl, p->n, nullptr, nullptr);
         if (pl.spec && f32_workspace_bytes(h, pl, p) > cap) pl.spec = false;
+        if (pl.regroup && f32_workspace_bytes(h, pl, p) > cap) pl.regroup = false;
         if (f32_workspace_bytes(h, pl, p) > cap) {
             if (h->tuning.split_segments > 1)
                 return fail(AIDW_ENOMEM,

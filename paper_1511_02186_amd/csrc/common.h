@@ -98,6 +98,11 @@ struct SplitWorkspace {
     // speculative sums (when the problem's spec_power is set):
     int* seg_ok;   // [segments][tiles] 1 where pass 1 formed the segment's sums
     int* tile_ok;  // [tiles] 1 where those sums stand for every segment
+    // Pass-2 regrouping (null p2order: pass 2 takes the pass-1 tiles): the
+    // positions sorted by their pass-2 loop (whole power, unscaled or not)
+    unsigned* p2key;  // [n]
+    int* p2hist;      // [256 * ceil(n / kOrderBlock)]
+    int* p2order;     // [n] pass-2 slot -> position
 };
 
 // Workspace of the speculative single-pass launch (spec_workspace_bytes):
@@ -157,6 +162,10 @@ int order_bits(int64_t n);
 size_t order_workspace_bytes(int64_t total, int blocks, int segments, int passes, OrderLaunch* L,
                              char* base);
 hipError_t launch_query_order(const OrderLaunch& L, hipStream_t stream);
+// Stable one-pass sort of positions 0..n-1 by keys[] < 256: order[slot] =
+// position (hist: 256 * ceil(n / kOrderBlock) ints of workspace).
+hipError_t launch_key_order(const unsigned* keys, int n, int* hist, int* order,
+                            hipStream_t stream);
 
 // One unit of batched work: 64 consecutive queries of one problem.
 struct BatchItem {

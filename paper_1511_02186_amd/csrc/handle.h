@@ -91,7 +91,7 @@ aidw_status device_alloc(aidw_t h, size_t bytes, void** out);
 void device_free(aidw_t h, void* p, size_t bytes);
 // Bytes of a split workspace; with ws/base given, also lays it out at base.
 size_t split_workspace_bytes(const SplitPlan& sp, int k, int64_t n, SplitWorkspace* ws,
-                             char* base);
+                             char* base, bool regroup = false);
 // Data segments of a problem under launch shape t (t.split_segments: 0
 // automatic, 1 never split, S forced).
 SplitPlan split_plan_for(const aidw_ctx* h, const aidw_tuning& t, int64_t m, int64_t n);

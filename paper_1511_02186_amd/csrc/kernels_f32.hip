@@ -911,13 +911,18 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_knn_merge(ProblemF32 p, S
     }
 }
 
-// Per-segment weighted sums: psum[(seg * 2 + {0: sum w, 1: sum w z}) * n + q].
-// Items of tiles whose speculative sums stand (tile_ok, may be null) have
-// nothing to do.
+// Per-segment weighted sums: psum[(seg * 2 + {0: sum w, 1: sum w z}) * n + q]
+// by pass-1 position q.  Items of tiles whose speculative sums stand
+// (tile_ok, may be null) have nothing to do.  With `regroup` (may be null) a
+// wave takes the 64 positions regroup[64 t ..] instead of tile t's: the
+// positions sorted by the loop their pass 2 takes, so that nearly every
+// wave takes one loop for all its lanes (pass 2 has no per-wave state but
+// that choice).
 __global__ __launch_bounds__(kGroupSize) void aidw_f32_wsum_part(ProblemF32 p, SplitPlan sp,
                                                                  const float* __restrict__ qpar,
                                                                  double* __restrict__ psum,
-                                                                 const int* __restrict__ tile_ok) {
+                                                                 const int* __restrict__ tile_ok,
+                                                                 const int* __restrict__ regroup) {
     const int wave = wave_id();
     const int seg = wave / sp.tiles;
     const int tile = wave - seg * sp.tiles;
@@ -925,18 +930,33 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_wsum_part(ProblemF32 p, S
     if (tile_ok && tile_ok[tile]) return;
     const int j0 = seg * sp.seg_len;
     const int j1 = seg_end(p.m, j0, sp.seg_len);
-    int qi[1], qs[1];
-    float qx[1], qy[1];
-    load_queries<1>(p, tile * kWaveSize, qi, qs, qx, qy);
-    const int c = qi[0] < p.n ? qi[0] : p.n - 1;
+    const int slot = tile * kWaveSize + lane_id();
+    const int sc = slot < p.n ? slot : p.n - 1;
+    const int c = regroup ? regroup[sc] : sc;  // pass-1 position
+    const int qs = query_at(p, c);
+    float qx[1] = {p.qx[qs]}, qy[1] = {p.qy[qs]};
     float na[1] = {qpar[c]}, aL0[1] = {qpar[p.n + c]};
     double Sw[1] = {0.0}, Swz[1] = {0.0};
     scan_wsum_any<1>(as_const(p.dx), as_const(p.dy), as_const(p.dz), j0, j1, qx, qy, na, aL0, Sw,
                      Swz, (int)qpar[3 * p.n + c], qpar[2 * p.n + c], p.zmax);
-    if (qi[0] < p.n) {
-        psum[((int64_t)seg * 2 + 0) * p.n + qi[0]] = Sw[0];
-        psum[((int64_t)seg * 2 + 1) * p.n + qi[0]] = Swz[0];
+    if (slot < p.n) {
+        psum[((int64_t)seg * 2 + 0) * p.n + c] = Sw[0];
+        psum[((int64_t)seg * 2 + 1) * p.n + c] = Swz[0];
     }
+}
+
+// The pass-2 loop of each position as a sort key: 2 A + 1 for the unscaled
+// and 2 A for the scaled loop of a whole power A, 1 for the exp2/log2 loop
+// of a query on a data point (the guarded form), 0 for the exp2/log2 loop.
+__global__ __launch_bounds__(256) void aidw_f32_pass2_keys(ProblemF32 p,
+                                                           const float* __restrict__ qpar,
+                                                           unsigned* __restrict__ keys) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= p.n) return;
+    const int ipw = (int)qpar[3 * p.n + c];
+    const float aL0 = qpar[p.n + c];
+    keys[c] = ipw != 0 ? (unsigned)(2 * ipw + (unscaled_ok(aL0, p.zmax) ? 1 : 0))
+                       : (coincident(aL0) ? 1u : 0u);
 }
 
 __global__ __launch_bounds__(kGroupSize) void aidw_f32_wsum_reduce(ProblemF32 p, SplitPlan sp,
@@ -1164,8 +1184,16 @@ hipError_t launch_split(const ProblemF32& p, const SplitPlan& sp, const SplitWor
                        ws);
     hipLaunchKernelGGL((aidw_f32_knn_merge<K>), dim3(g_query), dim3(kGroupSize), 0, stream, p, sp,
                        ws);
+    const int* regroup = nullptr;
+    if (ws.p2order && !p.spec_power) {
+        hipLaunchKernelGGL(aidw_f32_pass2_keys, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0,
+                           stream, p, ws.qpar, ws.p2key);
+        const hipError_t e = launch_key_order(ws.p2key, p.n, ws.p2hist, ws.p2order, stream);
+        if (e != hipSuccess) return e;
+        regroup = ws.p2order;
+    }
     hipLaunchKernelGGL(aidw_f32_wsum_part, dim3(g_part), dim3(kGroupSize), 0, stream, p, sp,
-                       ws.qpar, ws.psum, p.spec_power ? ws.tile_ok : nullptr);
+                       ws.qpar, ws.psum, p.spec_power ? ws.tile_ok : nullptr, regroup);
     hipLaunchKernelGGL(aidw_f32_wsum_reduce, dim3(g_query), dim3(kGroupSize), 0, stream, p, sp,
                        ws.psum);
     return hipGetLastError();
@@ -1286,7 +1314,8 @@ hipError_t launch_aidw_f32_pass2(const ProblemF32& p, SplitPlan sp, const float*
     if (p.n <= 0) return hipSuccess;
     sp.tiles = (int)((p.n + kWaveSize - 1) / kWaveSize);
     hipLaunchKernelGGL(aidw_f32_wsum_part, dim3(groups_for((int64_t)sp.segments * sp.tiles)),
-                       dim3(kGroupSize), 0, stream, p, sp, qpar, psum, (const int*)nullptr);
+                       dim3(kGroupSize), 0, stream, p, sp, qpar, psum, (const int*)nullptr,
+                       (const int*)nullptr);
     hipLaunchKernelGGL(aidw_f32_wsum_reduce, dim3((unsigned)((p.n + kGroupSize - 1) / kGroupSize)),
                        dim3(kGroupSize), 0, stream, p, sp, psum);
     return hipGetLastError();

@@ -169,14 +169,22 @@ __global__ __launch_bounds__(kWaveSize) void aidw_order_bbox(OrderLaunch L) {
     }
 }
 
-// The key of query i of segment s: from its coordinates in the first pass,
-// else from the previous pass's output.
-template <bool FIRST>
+// Where a pass finds the key of element i of segment s.
+enum KeySource {
+    kFromCoords = 0,  // first pass: the Morton code of the query's cell
+    kFromPrev = 1,    // later passes: the previous pass's output
+    kGiven = 2,       // a one-pass sort of keys the caller computed (value: i)
+};
+
+template <int SRC>
 __device__ __forceinline__ void key_of(const OrderLaunch& L, const OrderSeg& s, int si, int i,
                                        const unsigned* keys_in, const int* vals_in, unsigned& key,
                                        int& val) {
-    if (FIRST) {
+    if constexpr (SRC == kFromCoords) {
         key = morton_key(s, L.bbox[si], i);
+        val = i;
+    } else if constexpr (SRC == kGiven) {
+        key = keys_in[(int64_t)s.base + i];
         val = i;
     } else {
         key = keys_in[(int64_t)s.base + i];
@@ -185,7 +193,7 @@ __device__ __forceinline__ void key_of(const OrderLaunch& L, const OrderSeg& s, 
 }
 
 // Digit counts of one sort block b: hist[256 * b + digit].
-template <bool FIRST>
+template <int SRC>
 __global__ __launch_bounds__(kOrderThreads) void aidw_order_hist(OrderLaunch L, int shift,
                                                                  const unsigned* keys_in,
                                                                  const int* vals_in) {
@@ -201,7 +209,7 @@ __global__ __launch_bounds__(kOrderThreads) void aidw_order_hist(OrderLaunch L, 
         if (i < s.n) {
             unsigned key;
             int val;
-            key_of<FIRST>(L, s, si, i, keys_in, vals_in, key, val);
+            key_of<SRC>(L, s, si, i, keys_in, vals_in, key, val);
             atomicAdd(&h[(key >> shift) & 255u], 1);
         }
     }
@@ -240,7 +248,7 @@ __global__ __launch_bounds__(256) void aidw_order_scan(OrderLaunch L) {
 // (position order: chunk, then wave, then lane); within a wave a lane's rank
 // among equal digits is the number of lower lanes with its digit (ballots on
 // each digit bit); waves of a chunk and earlier chunks add their counts.
-template <bool FIRST>
+template <int SRC>
 __global__ __launch_bounds__(kOrderThreads) void aidw_order_scatter(OrderLaunch L, int shift,
                                                                     const unsigned* keys_in,
                                                                     const int* vals_in,
@@ -265,7 +273,7 @@ __global__ __launch_bounds__(kOrderThreads) void aidw_order_scatter(OrderLaunch 
         const bool valid = i < s.n;
         unsigned key = 0;
         int val = 0;
-        if (valid) key_of<FIRST>(L, s, si, i, keys_in, vals_in, key, val);
+        if (valid) key_of<SRC>(L, s, si, i, keys_in, vals_in, key, val);
         const unsigned d = (key >> shift) & 255u;
         unsigned long long same = __ballot(valid);
 #pragma unroll
@@ -311,19 +319,38 @@ hipError_t launch_query_order(const OrderLaunch& L, hipStream_t stream) {
         unsigned* kout = last ? nullptr : L.keys[pass & 1];
         int* vout = last ? L.order : L.vals[pass & 1];
         if (first)
-            hipLaunchKernelGGL((aidw_order_hist<true>), dim3((unsigned)L.blocks),
+            hipLaunchKernelGGL((aidw_order_hist<kFromCoords>), dim3((unsigned)L.blocks),
                                dim3(kOrderThreads), 0, stream, L, shift, kin, vin);
         else
-            hipLaunchKernelGGL((aidw_order_hist<false>), dim3((unsigned)L.blocks),
+            hipLaunchKernelGGL((aidw_order_hist<kFromPrev>), dim3((unsigned)L.blocks),
                                dim3(kOrderThreads), 0, stream, L, shift, kin, vin);
         hipLaunchKernelGGL(aidw_order_scan, dim3((unsigned)L.segments), dim3(256), 0, stream, L);
         if (first)
-            hipLaunchKernelGGL((aidw_order_scatter<true>), dim3((unsigned)L.blocks),
+            hipLaunchKernelGGL((aidw_order_scatter<kFromCoords>), dim3((unsigned)L.blocks),
                                dim3(kOrderThreads), 0, stream, L, shift, kin, vin, kout, vout);
         else
-            hipLaunchKernelGGL((aidw_order_scatter<false>), dim3((unsigned)L.blocks),
+            hipLaunchKernelGGL((aidw_order_scatter<kFromPrev>), dim3((unsigned)L.blocks),
                                dim3(kOrderThreads), 0, stream, L, shift, kin, vin, kout, vout);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_key_order(const unsigned* keys, int n, int* hist, int* order,
+                            hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    OrderLaunch L{};
+    const int blocks = (n + kOrderBlock - 1) / kOrderBlock;
+    L.one = OrderSeg{nullptr, nullptr, n, 0, 0, blocks, 0};
+    L.segments = 1;
+    L.blocks = blocks;
+    L.passes = 1;
+    L.hist = hist;
+    L.order = order;
+    hipLaunchKernelGGL((aidw_order_hist<kGiven>), dim3((unsigned)blocks), dim3(kOrderThreads), 0,
+                       stream, L, 0, keys, (const int*)nullptr);
+    hipLaunchKernelGGL(aidw_order_scan, dim3(1), dim3(256), 0, stream, L);
+    hipLaunchKernelGGL((aidw_order_scatter<kGiven>), dim3((unsigned)blocks), dim3(kOrderThreads), 0,
+                       stream, L, 0, keys, (const int*)nullptr, (unsigned*)nullptr, order);
     return hipGetLastError();
 }
 

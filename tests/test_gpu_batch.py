@@ -199,14 +199,37 @@ def _run(ctx, torch, inst, segments=0, diag=False, query_order=0):
 @pytest.mark.parametrize("k", [1, 10, 15, 32])
 def test_split_matches_unsplit_and_oracle(ctx, torch, segments, k):
     inst = workloads.clustered(m=50003, n=700, seed=segments + k, k=k, on_point=0.03)
-    whole, r0, a0, _ = _run(ctx, torch, inst, segments=1, diag=True)
-    split, r1, a1, _ = _run(ctx, torch, inst, segments=segments, diag=True)
+    # in the caller's order, where split pass 2 keeps the pass-1 tiles (and a
+    # query its wave mates, so its pass-2 loop)
+    whole, r0, a0, _ = _run(ctx, torch, inst, segments=1, diag=True, query_order=1)
+    split, r1, a1, _ = _run(ctx, torch, inst, segments=segments, diag=True, query_order=1)
     assert np.array_equal(r0, r1)  # same k nearest distances, same order of summation
     assert np.array_equal(a0, a1)
     assert np.allclose(split, whole, rtol=2e-7, atol=0)
     idx = np.arange(0, inst.n, 11)
     o, scale = ref(inst, idx)
     assert rel_err(split[idx], o, scale).max() <= TOL_F32
+
+
+@pytest.mark.parametrize("levels", [(1, 2, 3, 4, 5), (1, 2, 3, 4, 4.5), (2, 2, 2, 2, 2)])
+def test_split_pass2_regrouped_by_loop(ctx, torch, levels):
+    # split pass 2 regroups the positions by the loop they take (whole power,
+    # unscaled or not; exp2/log2; on a data point): every query is computed
+    # once, r_obs and alpha are untouched, and the outputs agree with the
+    # pass-1 tiles' (query_order = 1) to rounding and with the oracle
+    inst = workloads.clustered(m=60013, n=3001, seed=71, k=10, on_point=0.02)
+    inst.levels = levels
+    o1, r1, a1, _ = _run(ctx, torch, inst, segments=6, diag=True)
+    o0, r0, a0, _ = _run(ctx, torch, inst, segments=6, diag=True, query_order=1)
+    assert not np.isnan(o1).any()
+    assert np.array_equal(r0, r1) and np.array_equal(a0, a1)
+    assert np.allclose(o1, o0, rtol=1e-5, atol=1e-6 * np.abs(o0).max())
+    idx = np.unique(np.linspace(0, inst.n - 1, 40).astype(int))
+    o, scale = ref(inst, idx)
+    assert rel_err(o1[idx], o, scale).max() <= TOL_F32
+    on = np.asarray(inst.meta["on_point_queries"][:20])
+    o, scale = ref(inst, on)
+    assert rel_err(o1[on], o, scale).max() <= TOL_F32
 
 
 @pytest.mark.parametrize("m,n", [(4096, 1), (300000, 64), (1 << 20, 256), (65536, 5000)])

@@ -469,7 +469,13 @@ def _r_obs_alpha(ctx, torch, inst, track):
     ctx.bind_current_stream()
     p = ctx.problem(data_xy, data_z, query_xy, inst.k, out, inst.levels, inst.R_min, inst.R_max,
                     inst.area, r_obs=r, alpha=a, knn_idx=knn)
-    aidw.check(aidw.aidw_interpolate_ex(ctx.h, p))
+    # the caller's order: a split pass 2 keeps the pass-1 tiles, so both runs
+    # give each query the same pass-2 loop
+    ctx.set_tuning(query_order=1)
+    try:
+        aidw.check(aidw.aidw_interpolate_ex(ctx.h, p))
+    finally:
+        ctx.set_tuning()
     torch.cuda.synchronize()
     return r.cpu().numpy(), a.cpu().numpy(), out.cpu().numpy()
 

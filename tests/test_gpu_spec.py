@@ -186,12 +186,14 @@ def test_noalloc_takes_the_same_path(ctx, torch):
 def test_split_speculation_is_bit_identical(ctx, segments):
     # in the split kernels (speculate = 2) a pass-1 item's speculative sums
     # are the sums its pass-2 item would write, so the output does not depend
-    # on which tiles kept the speculation
+    # on which tiles kept the speculation.  Both runs in the caller's order:
+    # without speculation split pass 2 would otherwise regroup its waves by
+    # loop, which changes rounding
     inst = workloads.dense_patch(m=20000, n=2500, seed=26 + segments, k=15)
     data_xy, data_z, query_xy = aidw.to_device(inst)
     res = []
     for speculate in (2, 1):
-        ctx.set_tuning(0, 0, segments, speculate)
+        ctx.set_tuning(0, 0, segments, speculate, 1)
         try:
             res.append(tuple(t.cpu().numpy() for t in ctx.interpolate(
                 data_xy, data_z, query_xy, inst.k, inst.levels, inst.R_min, inst.R_max, inst.area,
@@ -202,7 +204,7 @@ def test_split_speculation_is_bit_identical(ctx, segments):
     assert np.array_equal(r0, r1) and np.array_equal(a0, a1)
     assert np.array_equal(o0, o1)
     err, a_ref = oracle_check(inst, o0)
-    fails = failing_tiles(a_ref, tile_order(ctx, inst))
+    fails = failing_tiles(a_ref, np.arange(inst.n))
     say("split %d: tiles off alpha_5 %d of %d, err %.3e" % (segments, fails, -(-inst.n // 64), err))
     assert 0 < fails < -(-inst.n // 64)
     assert err <= TOL_F32
