@@ -720,9 +720,12 @@ aidw_status aidw_describe_launch(aidw_t h, const aidw_problem* p, char* buf, siz
             d += "aidw_abs_max + aidw_f32_fused_spec" + k + "> + aidw_f32_defer_part + "
                  "aidw_f32_defer_reduce";
         else if (pl.sp.segments > 1)
-            d += "aidw_abs_max + aidw_f32_knn_part" + k + "> + aidw_f32_knn_merge" + k +
-                 "> + aidw_f32_wsum_part + aidw_f32_wsum_reduce (" +
-                 std::to_string(pl.sp.segments) + " data segments)";
+            d += "aidw_abs_max + aidw_f32_knn_part" + k + "> + aidw_f32_knn_merge" + k + "> + " +
+                 (pl.regroup ? "aidw_f32_pass2_keys + aidw_order_hist + aidw_order_scan + "
+                               "aidw_order_scatter (pass 2 regrouped by loop) + "
+                             : "") +
+                 "aidw_f32_wsum_part + aidw_f32_wsum_reduce (" + std::to_string(pl.sp.segments) +
+                 " data segments)";
         else
             d += "aidw_abs_max + aidw_f32_fused" + k + ", " + std::to_string(pl.cfg.q_per_lane) +
                  (p->knn_idx ? ", true>" : ", false>");

@@ -230,6 +230,14 @@ def test_split_pass2_regrouped_by_loop(ctx, torch, levels):
     on = np.asarray(inst.meta["on_point_queries"][:20])
     o, scale = ref(inst, on)
     assert rel_err(o1[on], o, scale).max() <= TOL_F32
+    for qo, named in ((0, True), (1, False)):
+        ctx.set_tuning(split_segments=6, query_order=qo)
+        try:
+            plan = _plan(ctx, torch, inst, inst.n, levels)
+        finally:
+            ctx.set_tuning()
+        assert ("pass 2 regrouped by loop" in plan) == named, plan
+        assert "aidw_f32_wsum_part" in plan
 
 
 @pytest.mark.parametrize("m,n", [(4096, 1), (300000, 64), (1 << 20, 256), (65536, 5000)])

@@ -199,13 +199,15 @@ def test_automatic_order_threshold(ctx, torch):
     small = workloads.uniform_unit(1000, 300, 3, 8)  # fewer than 1024 points
     ds = aidw.to_device(small)
     ps = ctx.problem(*ds, small.k, out, small.levels, small.R_min, small.R_max, small.area)
-    assert "aidw_order" not in aidw.aidw_describe_launch(ctx.h, ps)
+    # (the Morton order starts with aidw_order_box_part; a split problem's
+    # pass-2 regroup uses the sort kernels alone)
+    assert "aidw_order_box_part" not in aidw.aidw_describe_launch(ctx.h, ps)
     one_tile = ctx.problem(d[0], d[1], d[2][:, :64].contiguous(), inst.k, out[:64], inst.levels,
                            inst.R_min, inst.R_max, inst.area)
-    assert "aidw_order" not in aidw.aidw_describe_launch(ctx.h, one_tile)
+    assert "aidw_order_box_part" not in aidw.aidw_describe_launch(ctx.h, one_tile)
     ctx.set_tuning(query_order=1)
     try:
-        assert "aidw_order" not in aidw.aidw_describe_launch(ctx.h, p)
+        assert "aidw_order" not in aidw.aidw_describe_launch(ctx.h, p)  # nor the regroup
     finally:
         ctx.set_tuning()
 
