@@ -1267,12 +1267,19 @@ hipError_t launch_abs_max(const float* z, int m, float* out, hipStream_t s, int*
     return hipGetLastError();
 }
 
+// Most (tile, segment) items the deferred pass 2 can have: defer_plan gives
+// count tiles at most max(ceil(target / count), kDeferMaxL2Segments)
+// segments, so count * segments <= max(target + count, kDeferMaxL2Segments *
+// count), with count <= tiles.  The workspace and the launch both take this.
+static int64_t defer_items_max(int64_t tiles, int target) {
+    return std::max<int64_t>(target + tiles, kDeferMaxL2Segments * tiles);
+}
+
 size_t spec_workspace_bytes(int64_t n, int target, DeferWorkspace* ws, char* base) {
     const int64_t tiles = (n + kWaveSize - 1) / kWaveSize;
     const size_t a = 256;
     auto up = [&](size_t v) { return (v + a - 1) / a * a; };
-    // count * segments <= max(target + count, kDeferMaxL2Segments * count) items
-    const int64_t items = std::max<int64_t>(target + tiles, kDeferMaxL2Segments * tiles);
+    const int64_t items = defer_items_max(tiles, target);
     const size_t sizes[4] = {sizeof(int), sizeof(int) * (size_t)tiles, 4 * sizeof(float) * (size_t)n,
                              2 * sizeof(double) * (size_t)kWaveSize * (size_t)items};
     size_t off[4], bytes = 0;
@@ -1295,8 +1302,10 @@ hipError_t launch_spec_k(const ProblemF32& p, const DeferWorkspace& ws, hipStrea
     const int64_t tiles = (p.n + kWaveSize - 1) / kWaveSize;
     hipLaunchKernelGGL((aidw_f32_fused_spec<K>), dim3(groups_for(tiles)), dim3(kGroupSize), 0,
                        stream, SpecArgs{p, ws});
-    hipLaunchKernelGGL(aidw_f32_defer_part, dim3(groups_for(ws.target + tiles)), dim3(kGroupSize),
-                       0, stream, p, ws);
+    // one wave per possible item (the kernel reads the count and the plan;
+    // waves past count * segments return at once)
+    hipLaunchKernelGGL(aidw_f32_defer_part, dim3(groups_for(defer_items_max(tiles, ws.target))),
+                       dim3(kGroupSize), 0, stream, p, ws);
     hipLaunchKernelGGL(aidw_f32_defer_reduce,
                        dim3((unsigned)((tiles * kWaveSize + kGroupSize - 1) / kGroupSize)),
                        dim3(kGroupSize), 0, stream, p, ws);

@@ -130,6 +130,28 @@ def test_every_tile_deferred(ctx):
     assert err <= TOL_F32
 
 
+def test_many_deferred_tiles_in_l2_segments(ctx, torch):
+    # More failed tiles than target / 7 (target: one round of waves) over
+    # m = 2^20, where the deferred pass 2 cuts the data into eight L2-sized
+    # segments: count * 8 (tile, segment) items, more than target + count.
+    # Every item must run, and every deferred query come out right.
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    target = cus * 4 * 8
+    n = 64 * (target // 7 + 256)
+    inst = workloads.dense_patch(m=1 << 20, n=n, seed=32, k=15, patch_queries=1.0)
+    say("speculative pass: every query in the dense patch, m=%d n=%d" % (inst.m, inst.n))
+    out, _, alpha = run(ctx, inst)
+    fails = failing_tiles(alpha, tile_order(ctx, inst))
+    say("  tiles off alpha_5: %d of %d (deferred items %d, one round %d)"
+        % (fails, -(-inst.n // 64), 8 * fails, target))
+    assert 8 * fails > target + fails
+    assert not np.isnan(out).any()
+    idx = np.unique(np.linspace(0, inst.n - 1, 48).astype(np.int64))
+    err, _ = oracle_check(inst, out, idx)
+    say("  max rel err vs oracle %.3e" % err)
+    assert err <= TOL_F32
+
+
 def test_no_tile_deferred(ctx):
     inst = workloads.uniform_unit(1 << 16, 1 << 12, seed=22, k=15)
     out, _, alpha = run(ctx, inst)
