@@ -259,10 +259,11 @@ typedef struct aidw_tuning {
                                 when the speculative single pass applies) */
     int speculate;           /* 0: when alpha_5 is a whole power in [1, 8], pass 1
                                 of the unsplit launch also forms the pass-2 sums of
-                                that power, which stand for every 64-query tile
-                                whose queries all end at alpha_5 (pass 2 then runs
-                                only for the other tiles; results equal to the
-                                two-pass sums, bit for bit for the tiles that kept
+                                that power, which stand for every query that ends
+                                at alpha_5 with unscaled weights allowed (pass 2
+                                then runs only for the other queries; results equal
+                                to the two-pass kernel's to rounding, bit for bit
+                                in every 64-query tile whose queries all kept
                                 them); 1: never; 2: as 0, and also per data segment
                                 in the split kernels (pays on data where nearly
                                 every tile ends at alpha_5, such as uniform points;
@@ -339,7 +340,8 @@ aidw_status aidw_probe_issue_costs(aidw_t h, aidw_issue_costs* out);
  * (problem, 64-query tile) work items are ordered longest-first (by m) and
  * run one per wave in a single launch, so problems of very uneven size share
  * the GPU.  Results per query are bit-identical to aidw_interpolate_ex on
- * the same problem with q_per_lane = 1 and no split. */
+ * the same problem with q_per_lane = 1, no split and speculate = 1 (the
+ * two-pass kernel). */
 typedef struct aidw_batch* aidw_batch_t;
 
 /* Validate the problems, upload the work list and capture the launch as a

@@ -106,13 +106,14 @@ struct SplitWorkspace {
 };
 
 // Workspace of the speculative single-pass launch (spec_workspace_bytes):
-// tiles whose speculation fails leave their pass-2 terms in qpar and their
-// index in list, and the deferred pass 2 runs them in data segments.
+// queries whose speculative sums do not stand leave their pass-2 terms in
+// qpar and their position in list, and the deferred pass 2 runs them, 64 list
+// entries per wave, in data segments.
 struct DeferWorkspace {
-    int* count;    // tiles listed (zeroed by the max-|z| kernel before the scan)
-    int* list;     // [tiles] tile indices, in no particular order
-    float* qpar;   // [4][n] as SplitWorkspace::qpar, for listed tiles only
-    double* psum;  // [segments][2][count * 64] per-segment sums of listed tiles
+    int* count;    // queries listed (zeroed by the max-|z| kernel before the scan)
+    int* list;     // [n] positions of the listed queries, in no particular order
+    float* qpar;   // [4][n] as SplitWorkspace::qpar, for listed queries only
+    double* psum;  // [segments][2][groups * 64] per-segment sums, by list slot
     int target;    // waves the deferred pass 2 aims for (one round of the chip)
 };
 

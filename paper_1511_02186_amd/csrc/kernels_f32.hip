@@ -741,11 +741,12 @@ struct SpecArgs {
 typedef const __attribute__((address_space(4))) SpecArgs* spec_args_ptr;
 
 // One tile of the speculative launch: pass 1 with the sums of p.spec_power
-// (knn_speculative), and the output where the speculation held in every lane;
-// otherwise the tile's pass-2 terms go to ws.qpar and its index to ws.list,
+// (knn_speculative), and the output of every lane whose sums stand; the
+// other lanes' pass-2 terms go to ws.qpar and their positions to ws.list,
 // for the deferred pass 2.  Keeping pass 2 out of this kernel keeps it under
-// 80 SGPRs (8 waves per SIMD), and a failed tile's pass 2, split into data
-// segments, runs spread over the chip instead of as one long wave at the end.
+// 80 SGPRs (8 waves per SIMD), and the deferred queries' pass 2, split into
+// data segments, runs spread over the chip instead of as long waves at the
+// end.
 template <int K>
 __device__ __forceinline__ void spec_tile(const ProblemF32& p, spec_args_ptr ka, int tile) {
     int qi[1], qs[1];
@@ -764,20 +765,26 @@ __device__ __forceinline__ void spec_tile(const ProblemF32& p, spec_args_ptr ka,
     const int n = L->p.n;
     // the power whose sums cover every point
     const int spec = covered ? L->p.spec_power : 0;
-    // the sums stand when pass 2 would take the unscaled loop of that same
-    // power in this wave (the choice scan_wsum_any makes)
-    if (spec != 0 && __all(ipw == spec) && __all(unscaled_ok(aL0[0], L->p.zmax))) {
-        if (qi[0] < n) L->p.out[qs[0]] = (float)(Swz / Sw);
-        return;
-    }
-    float* const qpar = L->ws.qpar;
-    if (qi[0] < n) {
+    // A lane's sums stand when its pass 2 would be the unscaled loop of that
+    // same power: what a wave of such queries computes (scan_wsum_any's
+    // choice), bit for bit.
+    const bool keep = spec != 0 && ipw == spec && unscaled_ok(aL0[0], L->p.zmax);
+    if (keep && qi[0] < n) L->p.out[qs[0]] = (float)(Swz / Sw);
+    const bool defer = !keep && qi[0] < n;
+    const unsigned long long mask = __ballot(defer);
+    if (mask == 0) return;
+    // the wave's deferred lanes take consecutive list slots (one atomic)
+    int first = 0;
+    if (lane_id() == 0) first = atomicAdd(L->ws.count, __popcll(mask));
+    first = __builtin_amdgcn_readfirstlane(first);
+    if (defer) {
+        float* const qpar = L->ws.qpar;
         qpar[qi[0]] = na[0];
         qpar[n + qi[0]] = aL0[0];
         qpar[2 * n + qi[0]] = sqrtf(d2min[0]);
         qpar[3 * n + qi[0]] = (float)ipw;
+        L->ws.list[first + __popcll(mask & ((1ull << lane_id()) - 1ull))] = qi[0];
     }
-    if (lane_id() == 0) L->ws.list[atomicAdd(L->ws.count, 1)] = tile;
 }
 
 template <int K, int Q, bool TRACK>
@@ -972,16 +979,17 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_wsum_reduce(ProblemF32 p,
 }
 
 
-// ---- deferred pass 2 of the tiles whose speculation failed ------------------
-// `count` tiles (only known on the device) run as (tile, data segment) items,
-// S segments each with S chosen so that count * S is about ws.target waves
-// (one round of the chip): a few failed tiles then still fill the device.
-// Segments are whole 16-point batches of at least kDeferMinSegment points.
+// ---- deferred pass 2 of the queries whose speculation failed ----------------
+// `count` queries (only known on the device), in groups of 64 consecutive
+// list entries, run as (group, data segment) items, S segments each with S
+// chosen so that groups * S is about ws.target waves (one round of the
+// chip): a few deferred queries then still fill the device.  Segments are
+// whole 16-point batches of at least kDeferMinSegment points.
 constexpr int kDeferMinSegment = 2048;
 
 // At least ceil(m / kDeferL2Segment) segments (at most kDeferMaxL2Segments),
-// so that when many tiles fail the waves resident together read one
-// segment of about 1.5 MB of x, y, z that stays in the XCD's L2 (as the
+// so that when many queries are deferred the waves resident together read
+// one segment of about 1.5 MB of x, y, z that stays in the XCD's L2 (as the
 // grid mode's pass 2 does).
 constexpr int kDeferL2Segment = 131072;
 constexpr int kDeferMaxL2Segments = 8;
@@ -995,31 +1003,36 @@ __device__ __forceinline__ void defer_plan(int m, int count, int target, int& se
     segs = (int)(((int64_t)m + seg_len - 1) / seg_len);
 }
 
-// Item w: segment w / count of listed tile w % count (segment-major, so that
+__device__ __forceinline__ int defer_count(const DeferWorkspace& ws) {
+    return *(const __attribute__((address_space(4))) int*)ws.count;
+}
+
+// Item w: segment w / groups of list group w % groups (segment-major, so that
 // the waves resident together read the same data segment).  Sums go to
-// psum[(seg * 2 + {0, 1}) * count * 64 + position * 64 + lane].
+// psum[(seg * 2 + {0, 1}) * groups * 64 + list slot].
 __global__ __launch_bounds__(kGroupSize) void aidw_f32_defer_part(ProblemF32 p, DeferWorkspace ws) {
-    const int count = *(const __attribute__((address_space(4))) int*)ws.count;
+    const int count = defer_count(ws);
+    const int groups = (count + kWaveSize - 1) / kWaveSize;
     int segs, seg_len;
-    defer_plan(p.m, count, ws.target, segs, seg_len);
+    defer_plan(p.m, groups, ws.target, segs, seg_len);
     const int w = wave_id();
-    if (w >= count * segs) return;
-    const int seg = w / count;
-    const int pos = w - seg * count;
-    const int tile = __builtin_amdgcn_readfirstlane(ws.list[pos]);
+    if (w >= groups * segs) return;
+    const int seg = w / groups;
+    const int grp = w - seg * groups;
     const int j0 = seg * seg_len;
     const int j1 = seg_end(p.m, j0, seg_len);
-    int qi[1], qs[1];
-    float qx[1], qy[1];
-    load_queries<1>(p, tile * kWaveSize, qi, qs, qx, qy);
-    const int c = qi[0] < p.n ? qi[0] : p.n - 1;
+    const int slot = grp * kWaveSize + lane_id();
+    // lanes past the list's end repeat its last query and write slots that
+    // the reduction skips
+    const int c = ws.list[slot < count ? slot : count - 1];  // pass-1 position
+    const int qs = query_at(p, c);
     const float* qp = ws.qpar;
+    float qx[1] = {p.qx[qs]}, qy[1] = {p.qy[qs]};
     float na[1] = {qp[c]}, aL0[1] = {qp[p.n + c]};
     double Sw[1] = {0.0}, Swz[1] = {0.0};
     scan_wsum_any<1>(as_const(p.dx), as_const(p.dy), as_const(p.dz), j0, j1, qx, qy, na, aL0, Sw,
                      Swz, (int)qp[3 * p.n + c], qp[2 * p.n + c], p.zmax);
-    const int64_t slot = (int64_t)pos * kWaveSize + lane_id();
-    const int64_t stride = (int64_t)count * kWaveSize;
+    const int64_t stride = (int64_t)groups * kWaveSize;
     ws.psum[(int64_t)seg * 2 * stride + slot] = Sw[0];
     ws.psum[((int64_t)seg * 2 + 1) * stride + slot] = Swz[0];
 }
@@ -1027,21 +1040,19 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_defer_part(ProblemF32 p, 
 // The segments of each listed query added in order, then the ratio.
 __global__ __launch_bounds__(kGroupSize) void aidw_f32_defer_reduce(ProblemF32 p,
                                                                     DeferWorkspace ws) {
-    const int count = *(const __attribute__((address_space(4))) int*)ws.count;
+    const int count = defer_count(ws);
     const int t = blockIdx.x * kGroupSize + threadIdx.x;
-    const int pos = t / kWaveSize;
-    if (pos >= count) return;
-    const int q = ws.list[pos] * kWaveSize + (t - pos * kWaveSize);
-    if (q >= p.n) return;
+    if (t >= count) return;
+    const int groups = (count + kWaveSize - 1) / kWaveSize;
     int segs, seg_len;
-    defer_plan(p.m, count, ws.target, segs, seg_len);
-    const int64_t stride = (int64_t)count * kWaveSize;
+    defer_plan(p.m, groups, ws.target, segs, seg_len);
+    const int64_t stride = (int64_t)groups * kWaveSize;
     double Sw = 0.0, Swz = 0.0;
     for (int seg = 0; seg < segs; ++seg) {
         Sw += ws.psum[(int64_t)seg * 2 * stride + t];
         Swz += ws.psum[((int64_t)seg * 2 + 1) * stride + t];
     }
-    p.out[query_at(p, q)] = (float)(Swz / Sw);
+    p.out[query_at(p, ws.list[t])] = (float)(Swz / Sw);
 }
 
 // max |z| as the largest bit pattern of |z| (ordered like the values for
@@ -1267,10 +1278,11 @@ hipError_t launch_abs_max(const float* z, int m, float* out, hipStream_t s, int*
     return hipGetLastError();
 }
 
-// Most (tile, segment) items the deferred pass 2 can have: defer_plan gives
-// count tiles at most max(ceil(target / count), kDeferMaxL2Segments)
-// segments, so count * segments <= max(target + count, kDeferMaxL2Segments *
-// count), with count <= tiles.  The workspace and the launch both take this.
+// Most (group, segment) items the deferred pass 2 can have: defer_plan gives
+// g groups of 64 deferred queries at most max(ceil(target / g),
+// kDeferMaxL2Segments) segments, so g * segments <= max(target + g,
+// kDeferMaxL2Segments * g), with g <= tiles.  The workspace and the launch
+// both take this.
 static int64_t defer_items_max(int64_t tiles, int target) {
     return std::max<int64_t>(target + tiles, kDeferMaxL2Segments * tiles);
 }
@@ -1280,7 +1292,7 @@ size_t spec_workspace_bytes(int64_t n, int target, DeferWorkspace* ws, char* bas
     const size_t a = 256;
     auto up = [&](size_t v) { return (v + a - 1) / a * a; };
     const int64_t items = defer_items_max(tiles, target);
-    const size_t sizes[4] = {sizeof(int), sizeof(int) * (size_t)tiles, 4 * sizeof(float) * (size_t)n,
+    const size_t sizes[4] = {sizeof(int), sizeof(int) * (size_t)n, 4 * sizeof(float) * (size_t)n,
                              2 * sizeof(double) * (size_t)kWaveSize * (size_t)items};
     size_t off[4], bytes = 0;
     for (int i = 0; i < 4; ++i) {
@@ -1303,7 +1315,7 @@ hipError_t launch_spec_k(const ProblemF32& p, const DeferWorkspace& ws, hipStrea
     hipLaunchKernelGGL((aidw_f32_fused_spec<K>), dim3(groups_for(tiles)), dim3(kGroupSize), 0,
                        stream, SpecArgs{p, ws});
     // one wave per possible item (the kernel reads the count and the plan;
-    // waves past count * segments return at once)
+    // waves past groups * segments return at once)
     hipLaunchKernelGGL(aidw_f32_defer_part, dim3(groups_for(defer_items_max(tiles, ws.target))),
                        dim3(kGroupSize), 0, stream, p, ws);
     hipLaunchKernelGGL(aidw_f32_defer_reduce,

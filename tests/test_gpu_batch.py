@@ -78,7 +78,9 @@ def mixed_instances(count, seed):
 
 
 def run_alone(ctx, torch, dev):
-    ctx.set_tuning(q_per_lane=1, split_segments=1)
+    # the unsplit two-pass kernel (a batch item's arithmetic; the speculative
+    # single pass agrees with it to rounding)
+    ctx.set_tuning(q_per_lane=1, split_segments=1, speculate=1)
     try:
         i = dev.inst
         r = ctx.interpolate(dev.data_xy, dev.data_z, dev.query_xy, i.k, i.levels, i.R_min,
@@ -182,9 +184,9 @@ def test_batched_config_512_instances(ctx, torch):
 
 # ---- split-m ---------------------------------------------------------------
 
-def _run(ctx, torch, inst, segments=0, diag=False, query_order=0):
+def _run(ctx, torch, inst, segments=0, diag=False, query_order=0, speculate=0):
     data_xy, data_z, query_xy = aidw.to_device(inst)
-    ctx.set_tuning(split_segments=segments, query_order=query_order)
+    ctx.set_tuning(split_segments=segments, speculate=speculate, query_order=query_order)
     try:
         # no knn_idx: asking for the indices would keep m unsplit
         r = ctx.interpolate(data_xy, data_z, query_xy, inst.k, inst.levels, inst.R_min,
@@ -200,9 +202,12 @@ def _run(ctx, torch, inst, segments=0, diag=False, query_order=0):
 def test_split_matches_unsplit_and_oracle(ctx, torch, segments, k):
     inst = workloads.clustered(m=50003, n=700, seed=segments + k, k=k, on_point=0.03)
     # in the caller's order, where split pass 2 keeps the pass-1 tiles (and a
-    # query its wave mates, so its pass-2 loop)
-    whole, r0, a0, _ = _run(ctx, torch, inst, segments=1, diag=True, query_order=1)
-    split, r1, a1, _ = _run(ctx, torch, inst, segments=segments, diag=True, query_order=1)
+    # query its wave mates, so its pass-2 loop), against the two-pass kernel
+    # (in the speculative single pass a query that ends at alpha_5 keeps its
+    # whole-power sums whatever its wave mates do)
+    whole, r0, a0, _ = _run(ctx, torch, inst, segments=1, diag=True, query_order=1, speculate=1)
+    split, r1, a1, _ = _run(ctx, torch, inst, segments=segments, diag=True, query_order=1,
+                            speculate=1)
     assert np.array_equal(r0, r1)  # same k nearest distances, same order of summation
     assert np.array_equal(a0, a1)
     assert np.allclose(split, whole, rtol=2e-7, atol=0)
@@ -298,7 +303,27 @@ def test_automatic_split_boundary(ctx, torch, levels):
     split, r1, a1, _ = _run(ctx, torch, below, diag=True, query_order=1)
     assert np.array_equal(r0[: n - 64], r1)
     assert np.array_equal(a0[: n - 64], a1)
-    assert np.allclose(split, whole[: n - 64], rtol=2e-7, atol=0)
+    # Above the boundary a whole alpha_5 runs the speculative single pass, in
+    # which a query that ends at alpha_5 keeps its whole-power sums even when
+    # a wave mate leaves alpha_5; the split kernels then take the general
+    # loop for the whole wave.  Such tiles agree to the loops' rounding, the
+    # others to FP64 summation order.
+    mixed = np.zeros(n - 64, dtype=bool)
+    if levels[4] == int(levels[4]):
+        mixed = np.repeat((a1.reshape(-1, 64) != levels[4]).any(axis=1), 64)
+    w = whole[: n - 64]
+    diff = np.abs(split.astype(np.float64) - w)
+    say("tiles with a query off alpha_5: %d of %d; max rel diff there %.2e" % (
+        mixed.sum() // 64, (n - 64) // 64,
+        (diff[mixed] / np.abs(w[mixed])).max() if mixed.any() else 0.0))
+    assert np.allclose(split[~mixed], w[~mixed], rtol=2e-7, atol=0)
+    assert np.allclose(split, w, rtol=1e-5, atol=1e-6 * np.abs(w).max())
+    # the queries of such tiles that kept their sums, against the oracle
+    kept = np.flatnonzero(mixed & (a1 == levels[4]))
+    if kept.size:
+        idx = kept[np.linspace(0, kept.size - 1, min(16, kept.size)).astype(int)]
+        o, scale = ref(inst, idx)
+        assert rel_err(whole[idx], o, scale).max() <= TOL_F32
     idx = np.unique(np.linspace(0, n - 65, 48).astype(int))
     o, scale = ref(inst, idx)
     assert rel_err(whole[idx], o, scale).max() <= TOL_F32

@@ -47,9 +47,10 @@ def ref(inst, idx):
 
 def alone(ctx, torch, inst, split):
     # serving orders each job's queries as a single launch does (the
-    # automatic choice), so a fused job's tiles are the same
+    # automatic choice), so a fused job's tiles are the same; a fused job is
+    # the two-pass kernel's arithmetic (not the speculative single pass)
     data_xy, data_z, query_xy = aidw.to_device(inst)
-    ctx.set_tuning(q_per_lane=1, split_segments=0 if split else 1)
+    ctx.set_tuning(q_per_lane=1, split_segments=0 if split else 1, speculate=0 if split else 1)
     try:
         r = ctx.interpolate(data_xy, data_z, query_xy, inst.k, inst.levels, inst.R_min,
                             inst.R_max, inst.area)

@@ -1,8 +1,8 @@
 """The speculative single pass of the unsplit FP32-scaled kernel.
 
 When alpha_5 is a whole power, pass 1 also forms the unscaled pass-2 sums of
-that power; tiles whose 64 queries all end at alpha_5 are done after one scan,
-the others get pass 2 afterwards in data segments.  These tests force the
+that power; queries that end at alpha_5 are done after one scan, the others
+get pass 2 afterwards in data segments.  These tests force the
 unsplit launch (split_segments = 1) so that small problems take that path, and
 check it against the FP64 oracle and against the two-pass kernel (the
 deterministic handle runs that one), with tiles that keep the speculation,
@@ -110,8 +110,10 @@ def test_mixed_tiles_match_oracle_and_two_pass(ctx, ctx_det):
     # pass 1 is the same multiset scan: r_obs and alpha are bit-identical
     out2, r2, a2 = run(ctx_det, inst)
     assert np.array_equal(r_obs, r2) and np.array_equal(alpha, a2)
-    # tiles that kept the speculation reproduce the two-pass sums bit for bit;
-    # deferred tiles add their data segments in another grouping
+    # tiles whose queries all kept the speculation reproduce the two-pass
+    # sums bit for bit; in the other tiles a query that kept it has the sums
+    # of a whole-power wave, and a deferred one adds its data segments in
+    # another grouping
     keep = np.zeros(inst.n, dtype=bool)
     keep[order] = np.repeat(~tile_flags(alpha, order), 64)[: inst.n]
     assert keep.any()
