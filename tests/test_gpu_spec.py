@@ -122,6 +122,68 @@ def test_mixed_tiles_match_oracle_and_two_pass(ctx, ctx_det):
     assert np.max(np.abs(out.astype(np.float64) - out2)) <= 1e-6 * scale
 
 
+def test_kept_queries_of_failed_tiles(ctx, ctx_det):
+    # In a tile where one query ends just below alpha_5, the other 63 keep
+    # their speculative sums: bit for bit what the two-pass kernel gives them
+    # in waves of alpha_5 queries only (a problem of those queries alone),
+    # where the two-pass kernel on the mixed tiles takes the general loop.
+    # A tile whose early check gives the speculation up (on 1/32 of the
+    # points, so now and then for a near miss) runs pass 2 deferred instead.
+    # R_max = 3.5 puts R_90 (mu_R = 0.9) in the bulk of the R distribution of
+    # uniform data, so near misses abound; the other queries are taken well
+    # above it, and tiles are laid out in the caller's order.
+    import copy
+
+    base = workloads.uniform_unit(1 << 16, 20000, seed=33, k=15)
+    base.R_max = 3.5
+    _, r_all, a_all = run(ctx, base)
+    r90 = r_all[a_all == 5.0].min()
+    on = np.flatnonzero((a_all == 5.0) & (r_all >= 1.3 * r90))
+    near = np.flatnonzero((a_all >= 4.95) & (a_all < 5.0))
+    tiles = 16
+    assert on.size >= 63 * tiles and near.size >= tiles
+    pick = []
+    for t in range(tiles):
+        lanes = list(on[63 * t: 63 * (t + 1)])
+        lanes.insert(17, near[t])
+        pick.extend(lanes)
+    pick = np.asarray(pick)
+    inst = copy.copy(base)
+    inst.query_x = np.ascontiguousarray(base.query_x[pick])
+    inst.query_y = np.ascontiguousarray(base.query_y[pick])
+    data_xy, data_z, query_xy = aidw.to_device(inst)
+    res = []
+    for speculate in (0, 1):  # unsplit, caller's order: speculative, two-pass
+        ctx.set_tuning(0, 0, 1, speculate, 1)
+        try:
+            o, _, a, _ = ctx.interpolate(data_xy, data_z, query_xy, inst.k, inst.levels,
+                                         inst.R_min, inst.R_max, inst.area, diag=True,
+                                         knn=False)
+        finally:
+            ctx.set_tuning(0)
+        res.append((o.cpu().numpy(), a.cpu().numpy()))
+    (out, alpha), (two, alpha2) = res
+    assert np.array_equal(alpha, alpha2)
+    kept = alpha == 5.0
+    assert kept.sum() == 63 * tiles and np.all(~kept[17::64])
+    sub = copy.copy(inst)
+    sub.query_x = np.ascontiguousarray(inst.query_x[kept])
+    sub.query_y = np.ascontiguousarray(inst.query_y[kept])
+    out_sub, _, alpha_sub = run(ctx_det, sub)
+    assert np.all(alpha_sub == 5.0)
+    alone = np.full(inst.n, np.nan, dtype=np.float32)
+    alone[kept] = out_sub
+    same = ((out == alone) | ~kept).reshape(tiles, 64).all(axis=1)
+    differs = ((out != two) & kept).reshape(tiles, 64).any(axis=1)
+    say("tiles whose alpha_5 queries kept their sums: %d of %d" % ((same & differs).sum(), tiles))
+    assert (same & differs).sum() >= tiles // 2
+    assert np.allclose(out, two, rtol=1e-5, atol=1e-6 * np.abs(two).max())
+    err, _ = oracle_check(inst, out, np.arange(17, inst.n, 64))  # the near misses
+    assert err <= TOL_F32
+    err, _ = oracle_check(inst, out, np.arange(0, inst.n, 37))
+    assert err <= TOL_F32
+
+
 def test_every_tile_deferred(ctx):
     # clustered data with k = 8: few tiles keep alpha_5 everywhere
     inst = workloads.clustered(m=8192, n=1000, seed=21, k=8)
