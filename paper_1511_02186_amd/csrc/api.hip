@@ -717,8 +717,8 @@ aidw_status aidw_describe_launch(aidw_t h, const aidw_problem* p, char* buf, siz
                 "aidw_order_scatter) x " +
                 std::to_string(order_passes(pl.order_bits)) + " + ";
         if (pl.spec)
-            d += "aidw_abs_max + aidw_f32_fused_spec" + k + "> + aidw_f32_defer_part + "
-                 "aidw_f32_defer_reduce";
+            d += "aidw_abs_max + aidw_f32_fused_spec" + k + "> + aidw_f32_defer_list + "
+                 "aidw_f32_defer_part + aidw_f32_defer_reduce";
         else if (pl.sp.segments > 1)
             d += "aidw_abs_max + aidw_f32_knn_part" + k + "> + aidw_f32_knn_merge" + k + "> + " +
                  (pl.regroup ? "aidw_f32_pass2_keys + aidw_order_hist + aidw_order_scan + "

@@ -107,11 +107,14 @@ struct SplitWorkspace {
 
 // Workspace of the speculative single-pass launch (spec_workspace_bytes):
 // queries whose speculative sums do not stand leave their pass-2 terms in
-// qpar and their position in list, and the deferred pass 2 runs them, 64 list
-// entries per wave, in data segments.
+// qpar and a bit in their tile's mask; a list kernel turns the masks into
+// their positions in position order (so the deferred waves, and with them
+// each query's pass-2 loop, do not depend on timing), and the deferred pass
+// 2 runs them, 64 list entries per wave, in data segments.
 struct DeferWorkspace {
-    int* count;    // queries listed (zeroed by the max-|z| kernel before the scan)
-    int* list;     // [n] positions of the listed queries, in no particular order
+    int* count;    // queries listed (written by the list kernel)
+    int* list;     // [n] positions of the listed queries, ascending
+    unsigned long long* mask;  // [tiles] per tile: bit l set when lane l is deferred
     float* qpar;   // [4][n] as SplitWorkspace::qpar, for listed queries only
     double* psum;  // [segments][2][groups * 64] per-segment sums, by list slot
     int target;    // waves the deferred pass 2 aims for (one round of the chip)

@@ -742,7 +742,7 @@ typedef const __attribute__((address_space(4))) SpecArgs* spec_args_ptr;
 
 // One tile of the speculative launch: pass 1 with the sums of p.spec_power
 // (knn_speculative), and the output of every lane whose sums stand; the
-// other lanes' pass-2 terms go to ws.qpar and their positions to ws.list,
+// other lanes' pass-2 terms go to ws.qpar and their bits to ws.mask[tile],
 // for the deferred pass 2.  Keeping pass 2 out of this kernel keeps it under
 // 80 SGPRs (8 waves per SIMD), and the deferred queries' pass 2, split into
 // data segments, runs spread over the chip instead of as long waves at the
@@ -772,18 +772,16 @@ __device__ __forceinline__ void spec_tile(const ProblemF32& p, spec_args_ptr ka,
     if (keep && qi[0] < n) L->p.out[qs[0]] = (float)(Swz / Sw);
     const bool defer = !keep && qi[0] < n;
     const unsigned long long mask = __ballot(defer);
-    if (mask == 0) return;
-    // the wave's deferred lanes take consecutive list slots (one atomic)
-    int first = 0;
-    if (lane_id() == 0) first = atomicAdd(L->ws.count, __popcll(mask));
-    first = __builtin_amdgcn_readfirstlane(first);
+    // the tile index again from lane 0's position (a VGPR live anyway), so
+    // that no SGPR holds it through the scan
+    const int t = __builtin_amdgcn_readfirstlane(qi[0]) / kWaveSize;
+    if (lane_id() == 0) L->ws.mask[t] = mask;
     if (defer) {
         float* const qpar = L->ws.qpar;
         qpar[qi[0]] = na[0];
         qpar[n + qi[0]] = aL0[0];
         qpar[2 * n + qi[0]] = sqrtf(d2min[0]);
         qpar[3 * n + qi[0]] = (float)ipw;
-        L->ws.list[first + __popcll(mask & ((1ull << lane_id()) - 1ull))] = qi[0];
     }
 }
 
@@ -1001,6 +999,44 @@ __device__ __forceinline__ void defer_plan(int m, int count, int target, int& se
     seg_len = (int)(((int64_t)m + want - 1) / want);
     seg_len = (seg_len + 15) & ~15;
     segs = (int)(((int64_t)m + seg_len - 1) / seg_len);
+}
+
+// The deferred queries' positions in ascending order, and their count, from
+// the tiles' masks: one workgroup walks the tiles in chunks of 1024, a scan
+// of the masks' bit counts giving each tile its first list slot.
+constexpr int kDeferListThreads = 1024;
+
+__global__ __launch_bounds__(kDeferListThreads) void aidw_f32_defer_list(int tiles,
+                                                                          DeferWorkspace ws) {
+    constexpr int W = kDeferListThreads / kWaveSize;
+    __shared__ int wave_total[W];
+    const int lane = lane_id(), w = threadIdx.x / kWaveSize;
+    int carry = 0;
+    for (int t0 = 0; t0 < tiles; t0 += kDeferListThreads) {
+        const int t = t0 + (int)threadIdx.x;
+        unsigned long long mk = t < tiles ? ws.mask[t] : 0ull;
+        const int c = __popcll(mk);
+        int incl = c;  // inclusive scan of the bit counts within the wave
+        for (int o = 1; o < kWaveSize; o <<= 1) {
+            const int v = __shfl_up(incl, o);
+            if (lane >= o) incl += v;
+        }
+        if (lane == kWaveSize - 1) wave_total[w] = incl;
+        __syncthreads();
+        int before = 0, chunk = 0;
+        for (int v = 0; v < W; ++v) {
+            before += v < w ? wave_total[v] : 0;
+            chunk += wave_total[v];
+        }
+        int slot = carry + before + incl - c;
+        while (mk) {
+            ws.list[slot++] = t * kWaveSize + (__ffsll((long long)mk) - 1);
+            mk &= mk - 1ull;
+        }
+        carry += chunk;
+        __syncthreads();  // wave_total is rewritten by the next chunk
+    }
+    if (threadIdx.x == 0) *ws.count = carry;
 }
 
 __device__ __forceinline__ int defer_count(const DeferWorkspace& ws) {
@@ -1292,10 +1328,11 @@ size_t spec_workspace_bytes(int64_t n, int target, DeferWorkspace* ws, char* bas
     const size_t a = 256;
     auto up = [&](size_t v) { return (v + a - 1) / a * a; };
     const int64_t items = defer_items_max(tiles, target);
-    const size_t sizes[4] = {sizeof(int), sizeof(int) * (size_t)n, 4 * sizeof(float) * (size_t)n,
-                             2 * sizeof(double) * (size_t)kWaveSize * (size_t)items};
-    size_t off[4], bytes = 0;
-    for (int i = 0; i < 4; ++i) {
+    const size_t sizes[5] = {sizeof(int), sizeof(int) * (size_t)n, 4 * sizeof(float) * (size_t)n,
+                             2 * sizeof(double) * (size_t)kWaveSize * (size_t)items,
+                             sizeof(unsigned long long) * (size_t)tiles};
+    size_t off[5], bytes = 0;
+    for (int i = 0; i < 5; ++i) {
         off[i] = bytes;
         bytes += up(sizes[i]);
     }
@@ -1304,6 +1341,7 @@ size_t spec_workspace_bytes(int64_t n, int target, DeferWorkspace* ws, char* bas
         ws->list = reinterpret_cast<int*>(base + off[1]);
         ws->qpar = reinterpret_cast<float*>(base + off[2]);
         ws->psum = reinterpret_cast<double*>(base + off[3]);
+        ws->mask = reinterpret_cast<unsigned long long*>(base + off[4]);
         ws->target = target;
     }
     return bytes;
@@ -1314,6 +1352,8 @@ hipError_t launch_spec_k(const ProblemF32& p, const DeferWorkspace& ws, hipStrea
     const int64_t tiles = (p.n + kWaveSize - 1) / kWaveSize;
     hipLaunchKernelGGL((aidw_f32_fused_spec<K>), dim3(groups_for(tiles)), dim3(kGroupSize), 0,
                        stream, SpecArgs{p, ws});
+    hipLaunchKernelGGL(aidw_f32_defer_list, dim3(1), dim3(kDeferListThreads), 0, stream,
+                       (int)tiles, ws);
     // one wave per possible item (the kernel reads the count and the plan;
     // waves past groups * segments return at once)
     hipLaunchKernelGGL(aidw_f32_defer_part, dim3(groups_for(defer_items_max(tiles, ws.target))),

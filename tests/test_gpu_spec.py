@@ -184,6 +184,15 @@ def test_kept_queries_of_failed_tiles(ctx, ctx_det):
     assert err <= TOL_F32
 
 
+def test_deferred_queries_repeat_bit_for_bit(ctx):
+    # the deferred queries are listed in position order, so which of them
+    # share a deferred wave (and the pass-2 loop the wave takes) does not
+    # depend on the order in which tiles finish: runs repeat bit for bit
+    inst = workloads.dense_patch(m=20000, n=3000, seed=34, k=15)
+    outs = [run(ctx, inst)[0] for _ in range(3)]
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
 def test_every_tile_deferred(ctx):
     # clustered data with k = 8: few tiles keep alpha_5 everywhere
     inst = workloads.clustered(m=8192, n=1000, seed=21, k=8)
