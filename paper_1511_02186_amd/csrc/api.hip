@@ -384,7 +384,7 @@ hipError_t run_grid(aidw_t h, const aidw_problem* p, aidw_status* st_out) {
 struct F32Plan {
     aidw::LaunchF32 cfg;
     aidw::SplitPlan sp;
-    bool spec;  // the speculative single pass, with pass 2 deferred for failed tiles
+    bool spec;  // the speculative single pass, with pass 2 deferred for missed queries
     int order_bits;  // Morton bits per axis of the spatial tile order (0: caller's order)
     bool split_spec = false;  // speculative sums per data segment in the split kernels
     bool regroup = false;     // split pass 2 in waves regrouped by their loop

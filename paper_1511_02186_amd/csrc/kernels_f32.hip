@@ -443,14 +443,14 @@ __device__ __forceinline__ bool unscaled_ok(float aL0, const float* zmax) {
 // for every query whose R reaches R_max (Eq. 5 gives mu_R = 1 and Eq. 6
 // alpha_5); on uniform data that is nearly every query, because the mean of
 // k neighbour distances exceeds the expected first-neighbour distance of
-// Eq. 2 several times.  A wave whose 64 queries all end at alpha = A, with
-// unscaled weights allowed, has then finished both passes in one scan; the
-// others run pass 2 as usual.  The sums are those of pass 2's unscaled
-// whole-power loop bit for bit: the same batches aligned at j0, the same
-// order and the same rounding (scan_wsum_int<A, false>), so the result does
-// not depend on whether the speculation held.  The k-nearest list comes out
-// as pass 1's: the multiset of the k smallest squared distances does not
-// depend on the batching.
+// Eq. 2 several times.  A query that ends at alpha = A, with unscaled
+// weights allowed, has then finished both passes in one scan; the others
+// run pass 2 afterwards.  The sums are those of pass 2's unscaled
+// whole-power loop bit for bit (the loop a wave of such queries takes): the
+// same batches aligned at j0, the same order and the same rounding
+// (scan_wsum_int<A, false>).  The k-nearest list comes out as pass 1's: the
+// multiset of the k smallest squared distances does not depend on the
+// batching.
 template <int K, int A>
 __device__ __forceinline__ void scan_knn_wsum_int(cptr X, cptr Y, cptr Z, int j0, int j1, float qx,
                                                   float qy, float (&top)[K], double& Sw,
