@@ -1084,6 +1084,9 @@ __global__ __launch_bounds__(kGroupSize) void aidw_f32_defer_reduce(ProblemF32 p
     defer_plan(p.m, groups, ws.target, segs, seg_len);
     const int64_t stride = (int64_t)groups * kWaveSize;
     double Sw = 0.0, Swz = 0.0;
+    // in segment order; unrolled so that the loads of several segments are
+    // in flight together
+#pragma unroll 8
     for (int seg = 0; seg < segs; ++seg) {
         Sw += ws.psum[(int64_t)seg * 2 * stride + t];
         Swz += ws.psum[((int64_t)seg * 2 + 1) * stride + t];
@@ -1097,8 +1100,17 @@ template <int T>
 __device__ __forceinline__ void abs_max_block(const float* __restrict__ z, int m,
                                               float* __restrict__ out) {
     __shared__ unsigned s[T];
+    constexpr unsigned kAbs = 0x7fffffffu;
     unsigned v = 0;
-    for (int i = threadIdx.x; i < m; i += T) v = max(v, __float_as_uint(z[i]) & 0x7fffffffu);
+    int i = threadIdx.x;
+    // four independent loads per step keep more of the walk in flight
+    for (; i + 3 * T < m; i += 4 * T) {
+        const unsigned a = __float_as_uint(z[i]) & kAbs, b = __float_as_uint(z[i + T]) & kAbs;
+        const unsigned c = __float_as_uint(z[i + 2 * T]) & kAbs;
+        const unsigned d = __float_as_uint(z[i + 3 * T]) & kAbs;
+        v = max(v, max(max(a, b), max(c, d)));
+    }
+    for (; i < m; i += T) v = max(v, __float_as_uint(z[i]) & kAbs);
     s[threadIdx.x] = v;
     __syncthreads();
     for (int w = T / 2; w > 0; w >>= 1) {
